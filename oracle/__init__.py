@@ -1,0 +1,311 @@
+"""Plain FP64 CPU oracle for explicit leapfrog acoustic finite differences.
+
+TEST INFRASTRUCTURE ONLY.  This package is imported, called or executed only by
+``tests/``, by ``__graft_entry__.smoke()`` (to check one GPU result) and by the
+``cpu_baseline`` leg of ``bench.py``.  The GPU library never loads it and shares
+no code, header, table or helper with it; the two meet only at the seeded input
+generators in ``workloads.py``, which hold none of the method's arithmetic.
+
+What is computed, and where the paper (Medina, St-Cyr, Warburton, "High-Order
+Finite-differences on multi-threaded architectures using OCCA") defines it:
+
+* ``weights``   -- the symmetric xy stencil of Sec. 1 (R+1 weights w0..wR, the
+  centre weight taken per axis), with the weights fixed as the exact central
+  approximation of the second derivative: the unique symmetric stencil that is
+  exact on every polynomial of degree <= 2r+1 (Taylor conditions), solved in
+  rational arithmetic.  The paper prints the form, not the values.
+* ``ricker``    -- the Ricker forcing of Sec. 1, s = (1 - 2 pi^2 f^2 t^2) exp(-pi^2 f^2 t^2),
+  evaluated at t = n dt - t0 (the time shift t0 is this build's reading; the
+  paper prints none).
+* ``dt_max``    -- the von Neumann limit of the centred time scheme of Sec. 1 for
+  this stencil: dt^2 v^2 kappa_max^2 <= 4, with kappa_max^2 the largest
+  eigenvalue of -L.
+* ``laplacian``, ``forward`` -- the time scheme u^{n+1} - 2u^n + u^{n-1} = dt^2 F(u^n)
+  of Sec. 1 with the isotropic reduction F = v^2 L u + s(t) delta (Sec. 1, eq. (p)
+  with p = q), zero values for r points outside the domain (Sec. 1, last
+  paragraph), or a periodic box for closed-form tests.  Implemented in
+  ``fd_oracle.c`` as plain loops.
+* ``gradient``  -- the discrete adjoint (Lagrange multiplier recursion of the
+  forward scheme) of J = 1/2 sum (traces - observed)^2 with respect to v.
+  Not in the paper; its statement of the problem names full waveform inversion
+  as the application (Sec. 1).
+
+Every pin of this oracle lives in ``tests/test_oracle_*.py``.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+from fractions import Fraction
+from functools import lru_cache
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "fd_oracle.c")
+_LIB = os.path.join(_HERE, "libfd_oracle.so")
+
+__all__ = [
+    "build",
+    "weights",
+    "weights_f64",
+    "ricker",
+    "dt_max",
+    "laplacian",
+    "forward",
+    "gradient",
+    "misfit",
+    "linear_index",
+]
+
+
+# --------------------------------------------------------------------------- build / load
+
+
+def build(force: bool = True) -> str:
+    """Compile fd_oracle.c with gcc (IEEE FP64: no fast-math, no FMA contraction)."""
+    if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
+        return _LIB
+    tmp = _LIB + ".tmp"
+    cmd = [
+        "gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
+        "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wextra",
+        _SRC, "-o", tmp, "-lm",
+    ]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib_handle = None
+
+
+def _lib():
+    global _lib_handle
+    if _lib_handle is None:
+        if not os.path.exists(_LIB):
+            build()
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        I64 = ctypes.c_int64
+        lib.fdo_laplacian.argtypes = [ctypes.c_int, P, ctypes.c_int, P, ctypes.c_double, ctypes.c_int, P, P]
+        lib.fdo_forward.argtypes = [
+            ctypes.c_int, P, ctypes.c_int, P, ctypes.c_double, ctypes.c_double, P, ctypes.c_int,
+            I64, I64, P, P, I64, P, P, P, P, P,
+        ]
+        lib.fdo_adjoint.argtypes = [
+            ctypes.c_int, P, ctypes.c_int, P, ctypes.c_double, ctypes.c_double, P, ctypes.c_int,
+            I64, I64, P, P, P, P,
+        ]
+        for f in (lib.fdo_laplacian, lib.fdo_forward, lib.fdo_adjoint):
+            f.restype = ctypes.c_int
+        _lib_handle = lib
+    return _lib_handle
+
+
+def _ptr(a: np.ndarray | None):
+    if a is None:
+        return None
+    assert a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _check(status: int, what: str):
+    if status != 0:
+        raise ValueError(f"oracle {what} failed with status {status}")
+
+
+# --------------------------------------------------------------------------- stencil weights
+
+
+@lru_cache(maxsize=None)
+def weights(r: int) -> tuple[Fraction, ...]:
+    """Exact weights (w0, w1, ..., wr) of the symmetric radius-r stencil
+    h^2 u'' ~ w0 u_i + sum_l w_l (u_{i+l} + u_{i-l}) that is exact for every
+    polynomial of degree <= 2r+1 (Sec. 1 stencil form; weight values fixed by
+    the Taylor conditions, this build's reading).
+
+    Odd powers vanish by symmetry; the even powers x^{2k}, k = 0..r, give r+1
+    linear equations in r+1 unknowns (unit spacing, evaluated at 0):
+        k = 0:  w0 + 2 sum_l w_l = 0
+        k = 1:  2 sum_l w_l l^2 = 2
+        k >= 2: 2 sum_l w_l l^{2k} = 0
+    solved by Gaussian elimination over the rationals.
+    """
+    if not (1 <= r <= 16):
+        raise ValueError("r must be in [1, 16]")
+    nunk = r + 1
+    rows = []
+    for k in range(r + 1):
+        row = [Fraction(1 if k == 0 else 0)]  # coefficient of w0: 0^{2k}
+        row += [Fraction(2 * l ** (2 * k)) for l in range(1, r + 1)]
+        rhs = Fraction(2) if k == 1 else Fraction(0)
+        rows.append(row + [rhs])
+    # Gauss-Jordan elimination with exact pivots.
+    for col in range(nunk):
+        piv = next(i for i in range(col, nunk) if rows[i][col] != 0)
+        rows[col], rows[piv] = rows[piv], rows[col]
+        p = rows[col][col]
+        rows[col] = [x / p for x in rows[col]]
+        for i in range(nunk):
+            if i != col and rows[i][col] != 0:
+                f = rows[i][col]
+                rows[i] = [a - f * b for a, b in zip(rows[i], rows[col])]
+    return tuple(rows[i][nunk] for i in range(nunk))
+
+
+def weights_f64(r: int) -> np.ndarray:
+    """The exact weights rounded to the nearest double."""
+    return np.array([float(x) for x in weights(r)], dtype=np.float64)
+
+
+# --------------------------------------------------------------------------- source, CFL
+
+
+def ricker(nsamp: int, dt: float, f0: float = 15.0, t0: float | None = None) -> np.ndarray:
+    """Ricker samples s[n] = (1 - 2 pi^2 f^2 tau^2) exp(-pi^2 f^2 tau^2), tau = n dt - t0
+    (Sec. 1 forcing, f = 15 Hz).  The default shift t0 = 1.5 / f starts the wavelet
+    from ~1e-8 instead of from its peak (this build's reading)."""
+    if t0 is None:
+        t0 = 1.5 / f0
+    tau = np.arange(nsamp, dtype=np.float64) * dt - t0
+    a = (math.pi * f0 * tau) ** 2
+    return (1.0 - 2.0 * a) * np.exp(-a)
+
+
+def symbol_max(r: int) -> float:
+    """Largest value over theta of the 1-D stencil symbol -(w0 + 2 sum_l w_l cos(l theta)),
+    taken at theta = pi, where every term adds: -w0 - 2 sum_l w_l (-1)^l."""
+    w = weights(r)
+    s = -w[0] - 2 * sum(w[l] * (-1) ** l for l in range(1, r + 1))
+    return float(s)
+
+
+def dt_max(ndim: int, r: int, h: float, vmax: float) -> float:
+    """Stability limit of the leapfrog scheme: a Fourier mode with eigenvalue -kappa^2 of L
+    stays bounded iff dt^2 v^2 kappa^2 <= 4, and kappa_max^2 = ndim * symbol_max(r) / h^2."""
+    return 2.0 * h / (vmax * math.sqrt(ndim * symbol_max(r)))
+
+
+# --------------------------------------------------------------------------- grids
+
+
+def _dims(shape) -> tuple[int, np.ndarray]:
+    """Dense array shape (nz, ny, nx) / (ny, nx) / (nx,) -> ndim and n = [nx, ny, nz]."""
+    ndim = len(shape)
+    if ndim not in (1, 2, 3):
+        raise ValueError("ndim must be 1, 2 or 3")
+    rev = list(shape[::-1]) + [1] * (3 - ndim)
+    return ndim, np.array(rev, dtype=np.int64)
+
+
+def linear_index(shape, pos) -> np.ndarray:
+    """Linear indices of positions given as (x, y, z) tuples (x fastest)."""
+    ndim, n = _dims(shape)
+    pos = np.atleast_2d(np.asarray(pos, dtype=np.int64))
+    if pos.shape[1] != ndim:
+        raise ValueError(f"positions must have {ndim} coordinates")
+    idx = np.zeros(pos.shape[0], dtype=np.int64)
+    stride = 1
+    for a in range(ndim):
+        if np.any(pos[:, a] < 0) or np.any(pos[:, a] >= n[a]):
+            raise ValueError("position outside the grid")
+        idx += pos[:, a] * stride
+        stride *= int(n[a])
+    return idx
+
+
+def laplacian(u: np.ndarray, r: int, h: float, periodic: bool = False) -> np.ndarray:
+    """L u = h^-2 [ndim w0 u + sum_axes sum_l w_l (u_{+l} + u_{-l})] (Sec. 1 stencil form)."""
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    ndim, n = _dims(u.shape)
+    w = weights_f64(r)
+    out = np.empty_like(u)
+    _check(_lib().fdo_laplacian(ndim, _ptr(n), r, _ptr(w), h, int(periodic), _ptr(u), _ptr(out)), "laplacian")
+    return out
+
+
+def _source_arrays(shape, sources, nsteps):
+    nsrc = len(sources)
+    idx = np.zeros(nsrc, dtype=np.int64)
+    samples = np.zeros((nsteps, nsrc), dtype=np.float64)
+    for s, (pos, wav) in enumerate(sources):
+        idx[s] = linear_index(shape, [pos])[0]
+        wav = np.asarray(wav, dtype=np.float64)
+        k = min(nsteps, wav.shape[0])
+        samples[:k, s] = wav[:k]
+    return idx, np.ascontiguousarray(samples)
+
+
+def forward(v, h, dt, r, nsteps, sources=(), receivers=None, periodic=False, u0=None, um1=None,
+            store_states=False):
+    """Run ``nsteps`` leapfrog steps of u_tt = v^2 L u + sum_s s_s(t) delta_s.
+
+    v          velocity, dense (nz, ny, nx) / (ny, nx) / (nx,), m/s
+    sources    sequence of ((x[, y[, z]]), samples) -- sample n enters the step that
+               produces u^{n+1}, scaled by dt^2 / h^ndim (discrete delta)
+    receivers  int array [nrec, ndim] of (x, y, z) positions; traces[n][j] = u^{n+1}(x_j)
+    u0, um1    initial u^0 and u^{-1} (default zero)
+
+    Returns dict(u=u^T, u_prev=u^{T-1}, traces=[T, nrec], states=[T+1, ...] or None).
+    """
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    shape = v.shape
+    ndim, n = _dims(shape)
+    m = np.ascontiguousarray(v * v)
+    w = weights_f64(r)
+    u = np.zeros(shape) if u0 is None else np.array(u0, dtype=np.float64, copy=True)
+    up = np.zeros(shape) if um1 is None else np.array(um1, dtype=np.float64, copy=True)
+    src_idx, src = _source_arrays(shape, list(sources), nsteps)
+    if receivers is None or len(receivers) == 0:
+        rec_idx = np.zeros(0, dtype=np.int64)
+    else:
+        rec_idx = linear_index(shape, receivers)
+    traces = np.zeros((nsteps, rec_idx.shape[0]), dtype=np.float64)
+    states = np.zeros((nsteps + 1,) + shape, dtype=np.float64) if store_states else None
+    st = _lib().fdo_forward(
+        ndim, _ptr(n), r, _ptr(w), float(h), float(dt), _ptr(m), int(periodic), int(nsteps),
+        int(src_idx.shape[0]), _ptr(src_idx), _ptr(src), int(rec_idx.shape[0]), _ptr(rec_idx),
+        _ptr(traces), _ptr(u), _ptr(up), _ptr(states),
+    )
+    _check(st, "forward")
+    return {"u": u, "u_prev": up, "traces": traces, "states": states}
+
+
+def misfit(traces, observed) -> float:
+    """J = 1/2 sum_n sum_j (traces - observed)^2."""
+    d = np.asarray(traces, dtype=np.float64) - np.asarray(observed, dtype=np.float64)
+    return 0.5 * float(np.sum(d * d))
+
+
+def gradient(v, h, dt, r, nsteps, sources, receivers, observed, periodic=False):
+    """J and dJ/dv for J = 1/2 sum (traces - observed)^2 by the discrete adjoint.
+
+    Stores every forward state u^0..u^{T-1} (small grids only), runs the Lagrange
+    multiplier recursion in fd_oracle.c for dJ/dm (m = v^2), and returns
+    dJ/dv = 2 v dJ/dm.  Returns dict(J, grad_v, grad_m, traces).
+    """
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    shape = v.shape
+    ndim, n = _dims(shape)
+    fw = forward(v, h, dt, r, nsteps, sources, receivers, periodic=periodic, store_states=True)
+    resid = np.ascontiguousarray(fw["traces"] - np.asarray(observed, dtype=np.float64))
+    rec_idx = linear_index(shape, receivers)
+    states = np.ascontiguousarray(fw["states"][:nsteps])
+    m = np.ascontiguousarray(v * v)
+    w = weights_f64(r)
+    grad_m = np.zeros(shape, dtype=np.float64)
+    st = _lib().fdo_adjoint(
+        ndim, _ptr(n), r, _ptr(w), float(h), float(dt), _ptr(m), int(periodic), int(nsteps),
+        int(rec_idx.shape[0]), _ptr(rec_idx), _ptr(resid), _ptr(states), _ptr(grad_m),
+    )
+    _check(st, "adjoint")
+    return {
+        "J": misfit(fw["traces"], observed),
+        "grad_m": grad_m,
+        "grad_v": 2.0 * v * grad_m,
+        "traces": fw["traces"],
+    }

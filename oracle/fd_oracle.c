@@ -1,0 +1,241 @@
+/*
+ * fd_oracle.c -- plain FP64 CPU reference for explicit leapfrog time stepping
+ * of the acoustic wave equation  u_tt = v(x)^2 lap(u) + s(t) delta(x - x_s).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or
+ * call this file; only the test suite, the smoke check and the benchmark's
+ * CPU-baseline leg use it.  It shares no code with the GPU library.
+ *
+ * What it follows (Medina, St-Cyr, Warburton, "High-Order Finite-differences
+ * on multi-threaded architectures using OCCA"):
+ *   - Sec. 1, the centred second-order time scheme
+ *         u^{n+1} - 2 u^n + u^{n-1} = dt^2 F(u^n),   t^n = n dt;
+ *   - Sec. 1, the symmetric star stencil
+ *         h^2 (d_xx + d_yy) p ~ w0 p + sum_{l=1..R} w_l (p_{i+l} + p_{i-l} + p_{j+l} + p_{j-l}),
+ *     used here with one radius r and one spacing h on every axis;
+ *   - Sec. 1, the solution taken as zero for R points outside the domain
+ *     (zero Dirichlet ghost cells); a periodic mode exists for closed-form tests;
+ *   - Sec. 1, eq. (p): the point source s(t) delta(x - x_i), not multiplied by
+ *     the squared velocity.  A discrete delta is 1/h^ndim at the grid point, so
+ *     the source adds dt^2 s[n] / h^ndim to u^{n+1}.
+ *   - Isotropic reduction (end of Sec. 1): one field u, F = v^2 lap(u) + source.
+ *
+ * Layout: dense row-major [nz][ny][nx], x fastest.  ndim = 1 uses nx only,
+ * ndim = 2 uses [ny][nx].  All arithmetic is IEEE double, no reassociation.
+ * The only parallelism is an OpenMP loop over the slowest index of each
+ * point loop; every point is computed exactly as written.
+ */
+#include <math.h>
+#include <stddef.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define FDO_OK 0
+#define FDO_EINVAL -1
+#define FDO_ENOMEM -6
+
+typedef struct {
+    int ndim;
+    int64_t n[3]; /* nx, ny, nz; unused axes are 1 */
+    int r;
+    const double *w; /* w[0..r]: w0 (centre, per axis) and w_1..w_r */
+    double h;
+    int periodic;
+} grid_t;
+
+static int64_t npoints(const grid_t *g) { return g->n[0] * g->n[1] * g->n[2]; }
+
+/* Value of u at integer coordinates (i, j, k), which may lie outside the
+ * domain: zero ghost cells for the Dirichlet reading, wrap-around when periodic. */
+static double value_at(const grid_t *g, const double *u, int64_t i, int64_t j, int64_t k)
+{
+    int64_t c[3] = {i, j, k};
+    for (int a = 0; a < 3; ++a) {
+        if (g->periodic) {
+            c[a] = ((c[a] % g->n[a]) + g->n[a]) % g->n[a];
+        } else if (c[a] < 0 || c[a] >= g->n[a]) {
+            return 0.0;
+        }
+    }
+    return u[(c[2] * g->n[1] + c[1]) * g->n[0] + c[0]];
+}
+
+/* (L u) at one point: h^-2 [ ndim w0 u + sum_axes sum_l w_l (u_{+l} + u_{-l}) ],
+ * the stencil form of Sec. 1 applied on each active axis. */
+static double laplacian_at(const grid_t *g, const double *u, int64_t i, int64_t j, int64_t k)
+{
+    double acc = (double)g->ndim * g->w[0] * value_at(g, u, i, j, k);
+    for (int a = 0; a < g->ndim; ++a) {
+        for (int l = 1; l <= g->r; ++l) {
+            int64_t dp[3] = {0, 0, 0};
+            dp[a] = l;
+            double plus = value_at(g, u, i + dp[0], j + dp[1], k + dp[2]);
+            double minus = value_at(g, u, i - dp[0], j - dp[1], k - dp[2]);
+            acc += g->w[l] * (plus + minus);
+        }
+    }
+    return acc / (g->h * g->h);
+}
+
+static int check_grid(int ndim, const int64_t *n, int r, const double *w, double h)
+{
+    if (ndim < 1 || ndim > 3 || r < 1 || r > 16 || !w || !(h > 0.0))
+        return FDO_EINVAL;
+    for (int a = 0; a < 3; ++a) {
+        if (n[a] < 1) return FDO_EINVAL;
+        if (a >= ndim && n[a] != 1) return FDO_EINVAL;
+    }
+    return FDO_OK;
+}
+
+static grid_t make_grid(int ndim, const int64_t *n, int r, const double *w, double h, int periodic)
+{
+    grid_t g;
+    g.ndim = ndim;
+    g.n[0] = n[0];
+    g.n[1] = n[1];
+    g.n[2] = n[2];
+    g.r = r;
+    g.w = w;
+    g.h = h;
+    g.periodic = periodic;
+    return g;
+}
+
+/* out = L u over the whole grid. */
+int fdo_laplacian(int ndim, const int64_t *n, int r, const double *w, double h, int periodic,
+                  const double *u, double *out)
+{
+    int st = check_grid(ndim, n, r, w, h);
+    if (st) return st;
+    grid_t g = make_grid(ndim, n, r, w, h, periodic);
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < g.n[2]; ++k)
+        for (int64_t j = 0; j < g.n[1]; ++j)
+            for (int64_t i = 0; i < g.n[0]; ++i)
+                out[(k * g.n[1] + j) * g.n[0] + i] = laplacian_at(&g, u, i, j, k);
+    return FDO_OK;
+}
+
+/*
+ * Forward solve.  For n = 0 .. nsteps-1:
+ *     u^{n+1} = 2 u^n - u^{n-1} + dt^2 m (L u^n) + (dt^2 / h^ndim) sum_s src[n][s] e_{p_s}
+ *     traces[n][j] = u^{n+1}(x_j)
+ * with m = v^2 per point.
+ *   u_cur  in: u^0,      out: u^T
+ *   u_prev in: u^{-1},   out: u^{T-1}
+ *   src_idx[s]  linear index of source s; src[n * nsrc + s] its sample at step n
+ *   rec_idx[j]  linear index of receiver j; traces[n * nrec + j]
+ *   states      optional [nsteps + 1][N]: u^0 .. u^T
+ */
+int fdo_forward(int ndim, const int64_t *n, int r, const double *w, double h, double dt,
+                const double *m, int periodic, int64_t nsteps, int64_t nsrc, const int64_t *src_idx,
+                const double *src, int64_t nrec, const int64_t *rec_idx, double *traces,
+                double *u_cur, double *u_prev, double *states)
+{
+    int st = check_grid(ndim, n, r, w, h);
+    if (st) return st;
+    if (nsteps < 0 || nsrc < 0 || nrec < 0 || !(dt > 0.0)) return FDO_EINVAL;
+    grid_t g = make_grid(ndim, n, r, w, h, periodic);
+    const int64_t N = npoints(&g);
+    for (int64_t s = 0; s < nsrc; ++s)
+        if (src_idx[s] < 0 || src_idx[s] >= N) return FDO_EINVAL;
+    for (int64_t j = 0; j < nrec; ++j)
+        if (rec_idx[j] < 0 || rec_idx[j] >= N) return FDO_EINVAL;
+
+    double *u_next = (double *)malloc((size_t)N * sizeof(double));
+    if (!u_next) return FDO_ENOMEM;
+    const double dt2 = dt * dt;
+    const double src_scale = dt2 / pow(h, (double)ndim);
+
+    if (states) memcpy(states, u_cur, (size_t)N * sizeof(double));
+    for (int64_t step = 0; step < nsteps; ++step) {
+#pragma omp parallel for schedule(static)
+        for (int64_t k = 0; k < g.n[2]; ++k)
+            for (int64_t j = 0; j < g.n[1]; ++j)
+                for (int64_t i = 0; i < g.n[0]; ++i) {
+                    int64_t p = (k * g.n[1] + j) * g.n[0] + i;
+                    u_next[p] = 2.0 * u_cur[p] - u_prev[p] + dt2 * m[p] * laplacian_at(&g, u_cur, i, j, k);
+                }
+        for (int64_t s = 0; s < nsrc; ++s)
+            u_next[src_idx[s]] += src_scale * src[step * nsrc + s];
+        for (int64_t jr = 0; jr < nrec; ++jr)
+            traces[step * nrec + jr] = u_next[rec_idx[jr]];
+        /* rotate: u^{n-1} <- u^n, u^n <- u^{n+1} */
+        memcpy(u_prev, u_cur, (size_t)N * sizeof(double));
+        memcpy(u_cur, u_next, (size_t)N * sizeof(double));
+        if (states) memcpy(states + (step + 1) * N, u_cur, (size_t)N * sizeof(double));
+    }
+    free(u_next);
+    return FDO_OK;
+}
+
+/*
+ * Discrete adjoint of fdo_forward for the misfit J = 1/2 sum_n sum_j resid[n][j]^2,
+ * resid = traces - observed.  Written as the Lagrange multiplier recursion of the
+ * forward scheme (discretise, then differentiate):
+ *     lambda^{T+1} = lambda^{T+2} = 0,  for k = T .. 1:
+ *     lambda^k = 2 lambda^{k+1} - lambda^{k+2} + dt^2 L( m lambda^{k+1} ) + sum_j resid[k-1][j] e_{x_j}
+ *     dJ/dm   += dt^2 lambda^k (L u^{k-1})
+ * L is symmetric for the zero and periodic boundaries, so L^T (m .) = L (m .).
+ *   states   [nsteps][N]: u^0 .. u^{T-1} (as stored by fdo_forward)
+ *   grad_m   out: dJ/dm per point (m = v^2)
+ */
+int fdo_adjoint(int ndim, const int64_t *n, int r, const double *w, double h, double dt,
+                const double *m, int periodic, int64_t nsteps, int64_t nrec, const int64_t *rec_idx,
+                const double *resid, const double *states, double *grad_m)
+{
+    int st = check_grid(ndim, n, r, w, h);
+    if (st) return st;
+    if (nsteps < 0 || nrec < 0 || !(dt > 0.0)) return FDO_EINVAL;
+    grid_t g = make_grid(ndim, n, r, w, h, periodic);
+    const int64_t N = npoints(&g);
+    for (int64_t j = 0; j < nrec; ++j)
+        if (rec_idx[j] < 0 || rec_idx[j] >= N) return FDO_EINVAL;
+
+    double *lam1 = (double *)calloc((size_t)N, sizeof(double)); /* lambda^{k+1} */
+    double *lam2 = (double *)calloc((size_t)N, sizeof(double)); /* lambda^{k+2} */
+    double *lam0 = (double *)calloc((size_t)N, sizeof(double)); /* lambda^k     */
+    double *mlam = (double *)calloc((size_t)N, sizeof(double)); /* m lambda^{k+1} */
+    if (!lam1 || !lam2 || !lam0 || !mlam) {
+        free(lam1);
+        free(lam2);
+        free(lam0);
+        free(mlam);
+        return FDO_ENOMEM;
+    }
+    const double dt2 = dt * dt;
+    memset(grad_m, 0, (size_t)N * sizeof(double));
+
+    for (int64_t k = nsteps; k >= 1; --k) {
+        for (int64_t p = 0; p < N; ++p) mlam[p] = m[p] * lam1[p];
+#pragma omp parallel for schedule(static)
+        for (int64_t kk = 0; kk < g.n[2]; ++kk)
+            for (int64_t j = 0; j < g.n[1]; ++j)
+                for (int64_t i = 0; i < g.n[0]; ++i) {
+                    int64_t p = (kk * g.n[1] + j) * g.n[0] + i;
+                    lam0[p] = 2.0 * lam1[p] - lam2[p] + dt2 * laplacian_at(&g, mlam, i, j, kk);
+                }
+        for (int64_t jr = 0; jr < nrec; ++jr)
+            lam0[rec_idx[jr]] += resid[(k - 1) * nrec + jr];
+        const double *u_km1 = states + (k - 1) * N;
+#pragma omp parallel for schedule(static)
+        for (int64_t kk = 0; kk < g.n[2]; ++kk)
+            for (int64_t j = 0; j < g.n[1]; ++j)
+                for (int64_t i = 0; i < g.n[0]; ++i) {
+                    int64_t p = (kk * g.n[1] + j) * g.n[0] + i;
+                    grad_m[p] += dt2 * lam0[p] * laplacian_at(&g, u_km1, i, j, kk);
+                }
+        /* rotate: lambda^{k+2} <- lambda^{k+1}, lambda^{k+1} <- lambda^k */
+        double *t = lam2;
+        lam2 = lam1;
+        lam1 = lam0;
+        lam0 = t;
+    }
+    free(lam1);
+    free(lam2);
+    free(lam0);
+    free(mlam);
+    return FDO_OK;
+}
