@@ -71,7 +71,7 @@ def build(force: bool = True) -> str:
         return _LIB
     tmp = _LIB + ".tmp"
     cmd = [
-        "gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
+        "gcc", "-O3", "-std=c11", "-fPIC", "-shared", "-fopenmp",
         "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wextra",
         _SRC, "-o", tmp, "-lm",
     ]

@@ -61,17 +61,46 @@ static double value_at(const grid_t *g, const double *u, int64_t i, int64_t j, i
     return u[(c[2] * g->n[1] + c[1]) * g->n[0] + c[0]];
 }
 
+/* A copy of u with g->r ghost cells on each side of every active axis, filled by
+ * value_at (zeros, or wrapped values when periodic).  The stencil then reads
+ * neighbours by plain indexing; the values it sees are exactly value_at's. */
+typedef struct {
+    int64_t pn[3]; /* padded extents */
+    int64_t pad[3];
+    double *data;
+} padded_t;
+
+static int pad_field(const grid_t *g, const double *u, padded_t *pf)
+{
+    for (int a = 0; a < 3; ++a) {
+        pf->pad[a] = a < g->ndim ? g->r : 0;
+        pf->pn[a] = g->n[a] + 2 * pf->pad[a];
+    }
+    if (!pf->data) {
+        pf->data = (double *)malloc((size_t)(pf->pn[0] * pf->pn[1] * pf->pn[2]) * sizeof(double));
+        if (!pf->data) return FDO_ENOMEM;
+    }
+    double *d = pf->data;
+    const int64_t px = pf->pn[0], py = pf->pn[1];
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < pf->pn[2]; ++k)
+        for (int64_t j = 0; j < py; ++j)
+            for (int64_t i = 0; i < px; ++i)
+                d[(k * py + j) * px + i] = value_at(g, u, i - pf->pad[0], j - pf->pad[1], k - pf->pad[2]);
+    return FDO_OK;
+}
+
 /* (L u) at one point: h^-2 [ ndim w0 u + sum_axes sum_l w_l (u_{+l} + u_{-l}) ],
  * the stencil form of Sec. 1 applied on each active axis. */
-static double laplacian_at(const grid_t *g, const double *u, int64_t i, int64_t j, int64_t k)
+static double laplacian_at(const grid_t *g, const padded_t *pf, int64_t i, int64_t j, int64_t k)
 {
-    double acc = (double)g->ndim * g->w[0] * value_at(g, u, i, j, k);
+    const int64_t stride[3] = {1, pf->pn[0], pf->pn[0] * pf->pn[1]};
+    const double *c = pf->data + ((k + pf->pad[2]) * pf->pn[1] + (j + pf->pad[1])) * pf->pn[0] + (i + pf->pad[0]);
+    double acc = (double)g->ndim * g->w[0] * c[0];
     for (int a = 0; a < g->ndim; ++a) {
         for (int l = 1; l <= g->r; ++l) {
-            int64_t dp[3] = {0, 0, 0};
-            dp[a] = l;
-            double plus = value_at(g, u, i + dp[0], j + dp[1], k + dp[2]);
-            double minus = value_at(g, u, i - dp[0], j - dp[1], k - dp[2]);
+            double plus = c[l * stride[a]];
+            double minus = c[-l * stride[a]];
             acc += g->w[l] * (plus + minus);
         }
     }
@@ -110,11 +139,15 @@ int fdo_laplacian(int ndim, const int64_t *n, int r, const double *w, double h, 
     int st = check_grid(ndim, n, r, w, h);
     if (st) return st;
     grid_t g = make_grid(ndim, n, r, w, h, periodic);
+    padded_t pf = {{0, 0, 0}, {0, 0, 0}, NULL};
+    st = pad_field(&g, u, &pf);
+    if (st) return st;
 #pragma omp parallel for schedule(static)
     for (int64_t k = 0; k < g.n[2]; ++k)
         for (int64_t j = 0; j < g.n[1]; ++j)
             for (int64_t i = 0; i < g.n[0]; ++i)
-                out[(k * g.n[1] + j) * g.n[0] + i] = laplacian_at(&g, u, i, j, k);
+                out[(k * g.n[1] + j) * g.n[0] + i] = laplacian_at(&g, &pf, i, j, k);
+    free(pf.data);
     return FDO_OK;
 }
 
@@ -146,17 +179,22 @@ int fdo_forward(int ndim, const int64_t *n, int r, const double *w, double h, do
 
     double *u_next = (double *)malloc((size_t)N * sizeof(double));
     if (!u_next) return FDO_ENOMEM;
+    padded_t pf = {{0, 0, 0}, {0, 0, 0}, NULL};
     const double dt2 = dt * dt;
     const double src_scale = dt2 / pow(h, (double)ndim);
 
     if (states) memcpy(states, u_cur, (size_t)N * sizeof(double));
     for (int64_t step = 0; step < nsteps; ++step) {
+        if (pad_field(&g, u_cur, &pf)) {
+            free(u_next);
+            return FDO_ENOMEM;
+        }
 #pragma omp parallel for schedule(static)
         for (int64_t k = 0; k < g.n[2]; ++k)
             for (int64_t j = 0; j < g.n[1]; ++j)
                 for (int64_t i = 0; i < g.n[0]; ++i) {
                     int64_t p = (k * g.n[1] + j) * g.n[0] + i;
-                    u_next[p] = 2.0 * u_cur[p] - u_prev[p] + dt2 * m[p] * laplacian_at(&g, u_cur, i, j, k);
+                    u_next[p] = 2.0 * u_cur[p] - u_prev[p] + dt2 * m[p] * laplacian_at(&g, &pf, i, j, k);
                 }
         for (int64_t s = 0; s < nsrc; ++s)
             u_next[src_idx[s]] += src_scale * src[step * nsrc + s];
@@ -168,6 +206,7 @@ int fdo_forward(int ndim, const int64_t *n, int r, const double *w, double h, do
         if (states) memcpy(states + (step + 1) * N, u_cur, (size_t)N * sizeof(double));
     }
     free(u_next);
+    free(pf.data);
     return FDO_OK;
 }
 
@@ -207,25 +246,35 @@ int fdo_adjoint(int ndim, const int64_t *n, int r, const double *w, double h, do
     }
     const double dt2 = dt * dt;
     memset(grad_m, 0, (size_t)N * sizeof(double));
+    padded_t pf = {{0, 0, 0}, {0, 0, 0}, NULL};
+    int status = FDO_OK;
 
     for (int64_t k = nsteps; k >= 1; --k) {
         for (int64_t p = 0; p < N; ++p) mlam[p] = m[p] * lam1[p];
+        if (pad_field(&g, mlam, &pf)) {
+            status = FDO_ENOMEM;
+            break;
+        }
 #pragma omp parallel for schedule(static)
         for (int64_t kk = 0; kk < g.n[2]; ++kk)
             for (int64_t j = 0; j < g.n[1]; ++j)
                 for (int64_t i = 0; i < g.n[0]; ++i) {
                     int64_t p = (kk * g.n[1] + j) * g.n[0] + i;
-                    lam0[p] = 2.0 * lam1[p] - lam2[p] + dt2 * laplacian_at(&g, mlam, i, j, kk);
+                    lam0[p] = 2.0 * lam1[p] - lam2[p] + dt2 * laplacian_at(&g, &pf, i, j, kk);
                 }
         for (int64_t jr = 0; jr < nrec; ++jr)
             lam0[rec_idx[jr]] += resid[(k - 1) * nrec + jr];
         const double *u_km1 = states + (k - 1) * N;
+        if (pad_field(&g, u_km1, &pf)) {
+            status = FDO_ENOMEM;
+            break;
+        }
 #pragma omp parallel for schedule(static)
         for (int64_t kk = 0; kk < g.n[2]; ++kk)
             for (int64_t j = 0; j < g.n[1]; ++j)
                 for (int64_t i = 0; i < g.n[0]; ++i) {
                     int64_t p = (kk * g.n[1] + j) * g.n[0] + i;
-                    grad_m[p] += dt2 * lam0[p] * laplacian_at(&g, u_km1, i, j, kk);
+                    grad_m[p] += dt2 * lam0[p] * laplacian_at(&g, &pf, i, j, kk);
                 }
         /* rotate: lambda^{k+2} <- lambda^{k+1}, lambda^{k+1} <- lambda^k */
         double *t = lam2;
@@ -237,5 +286,6 @@ int fdo_adjoint(int ndim, const int64_t *n, int r, const double *w, double h, do
     free(lam2);
     free(lam0);
     free(mlam);
-    return FDO_OK;
+    free(pf.data);
+    return status;
 }
