@@ -1,0 +1,258 @@
+/*
+ * fdwave.h -- C ABI of the MI355X (gfx950) library for explicit leapfrog time
+ * stepping of the acoustic wave equation
+ *
+ *     u_tt = v(x)^2 lap(u) + sum_s s_s(t) delta(x - x_s)
+ *
+ * on a regular 2-D or 3-D grid of spacing h, with a radius-r (order 2r)
+ * central-difference star stencil and the centred second-order time scheme
+ *
+ *     u^{n+1} = 2 u^n - u^{n-1} + dt^2 v^2 L u^n + (dt^2 / h^ndim) sum_s s_s[n] e_{x_s}.
+ *
+ * The problem statement follows Medina, St-Cyr and Warburton, "High-Order
+ * Finite-differences on multi-threaded architectures using OCCA", Sec. 1: the
+ * time scheme, the symmetric stencil form, the zero solution for r points
+ * outside the domain, the point source s(t) delta(x - x_i) that is not scaled
+ * by the velocity, and the Ricker forcing; its isotropic reduction (end of
+ * Sec. 1) gives the single-field equation above.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Every function returns an fd_status (0 on success, < 0 on failure) unless
+ *    stated otherwise.  No C++ exception crosses the ABI.  fd_last_error()
+ *    returns a thread-local message for the last failure on the calling thread.
+ *  - Grids: n[0] = nx (fastest, contiguous), n[1] = ny, n[2] = nz.  A 2-D grid
+ *    has ndim = 2 and n[2] = 1.  Dense arrays are row-major [nz][ny][nx]
+ *    (3-D) or [ny][nx] (2-D).  Positions are (x, y, z) index triples.
+ *  - "device" pointers are HIP device memory on the current device; "host"
+ *    pointers are ordinary host memory read during the call only.
+ *  - The library never allocates device memory.  All device memory a context
+ *    uses is one caller-owned workspace (fd_workspace_bytes) plus the buffers
+ *    passed to the calls below.
+ *  - A context is bound to one HIP stream (hipStream_t passed as void*; NULL is
+ *    the null stream).  Every device operation is enqueued on it
+ *    asynchronously.  A context is not thread-safe; different contexts are
+ *    independent.  Argument errors are detected before anything is enqueued.
+ *  - Asynchronous device faults are reported as FD_E_DEVICE by fd_sync (or the
+ *    next call that synchronises); the context is then poisoned and only
+ *    fd_destroy remains valid on it.
+ *  - dtype FD_F32 stores and computes the wavefield in float; FD_F64 in double.
+ */
+#ifndef FDWAVE_H
+#define FDWAVE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fd_ctx fd_ctx;
+typedef struct fd_batch fd_batch;
+
+typedef enum {
+    FD_OK = 0,
+    FD_E_INVAL = -1,    /* bad argument (ndim, r, h, dt, sizes, null pointer) */
+    FD_E_RANGE = -2,    /* position outside the grid, capacity or maximum exceeded */
+    FD_E_UNSTABLE = -3, /* dt above the stability limit fd_dt_max for max(v) */
+    FD_E_STATE = -4,    /* call not valid in the context's current state */
+    FD_E_DEVICE = -5,   /* HIP runtime or kernel error; context poisoned */
+    FD_E_NOMEM = -6     /* workspace smaller than fd_workspace_bytes */
+} fd_status;
+
+typedef enum { FD_F32 = 0, FD_F64 = 1 } fd_dtype;
+
+/* FD_BC_ZERO: the solution is zero on r ghost cells outside every face (Sec. 1,
+ * last paragraph).  FD_BC_PERIODIC: the grid wraps around (used to test the
+ * scheme against closed-form standing waves; not supported by fd_batch). */
+typedef enum { FD_BC_ZERO = 0, FD_BC_PERIODIC = 1 } fd_bc;
+
+/* layout flag for state copies */
+typedef enum { FD_DENSE = 0, FD_PADDED = 1 } fd_layout;
+
+typedef struct {
+    int32_t ndim;  /* 2 or 3 */
+    int64_t n[3];  /* nx, ny, nz (nz = 1 when ndim = 2); each >= 1 */
+} fd_grid;
+
+/* ----------------------------------------------------------------- stencil and limits */
+
+/* Exact central weights of the radius-r second-derivative stencil on a unit grid,
+ * h^2 u'' ~ w[0] u_i + sum_{l=1..r} w[l] (u_{i+l} + u_{i-l})  (Sec. 1, stencil form;
+ * the weights are those exact for polynomials of degree <= 2r+1).
+ * w: host, r+1 doubles, written.  1 <= r <= 8. */
+int fd_weights(int r, double *w);
+
+/* Von Neumann limit of the leapfrog scheme for this stencil:
+ * dt_max = 2 h / (vmax sqrt(ndim S_r)), S_r = -w0 + 2 sum |w_l| the largest value of
+ * the 1-D symbol.  Returns a negative value for invalid arguments. */
+double fd_dt_max(int ndim, int r, double h, double vmax);
+
+/* ----------------------------------------------------------------- memory planning */
+
+/* Device bytes of one padded wavefield of this grid (the unit of checkpoints and of the
+ * recompute ring used by the adjoint).  Layout: x-fastest rows with a 64-byte aligned
+ * interior, r zero ghost planes/rows on every face plus alignment padding; the padding
+ * must stay zero.  *bytes written. */
+int fd_field_bytes(const fd_grid *g, int r, fd_dtype dtype, size_t *bytes);
+
+/* Device bytes of the workspace a context needs: two padded wavefields, the padded
+ * coefficient field c = (v dt / h)^2, and the source/receiver tables for at most
+ * max_sources sources and max_receivers receivers.  *bytes written. */
+int fd_workspace_bytes(const fd_grid *g, int r, fd_dtype dtype, int64_t max_sources,
+                       int64_t max_receivers, size_t *bytes);
+
+/* ----------------------------------------------------------------- lifecycle */
+
+/* Create a context (Sec. 1 problem statement: grid, stencil radius, spacing, time step
+ * and velocity).
+ *   velocity   device, dense, dtype, >0 m/s; read during the call only (converted to
+ *              c = (v dt / h)^2 in the workspace by a device kernel)
+ *   workspace  device, >= fd_workspace_bytes(...) bytes, 256-byte aligned; borrowed
+ *              until fd_destroy; zeroed here (both wavefields start at zero, step 0)
+ *   stream     hipStream_t the context enqueues on
+ * Errors: FD_E_INVAL (ndim not 2/3, r not in [1, 8], h or dt <= 0, null pointers,
+ * non-positive velocity), FD_E_NOMEM (workspace too small), FD_E_UNSTABLE
+ * (dt > fd_dt_max(ndim, r, h, max v)), FD_E_DEVICE.  Synchronises the stream once
+ * (to read max/min of v). */
+int fd_create(fd_ctx **out, const fd_grid *g, int r, double h, double dt, const void *velocity,
+              fd_dtype dtype, fd_bc bc, void *workspace, size_t ws_bytes, int64_t max_sources,
+              int64_t max_receivers, void *stream);
+
+int fd_destroy(fd_ctx *ctx);
+
+/* Rebind the context to another stream (e.g. after a caller switches streams). */
+int fd_set_stream(fd_ctx *ctx, void *stream);
+
+/* ----------------------------------------------------------------- source and receivers */
+
+/* Add a point source (Sec. 1, eq. (p): s(t) delta(x - x_i)).
+ *   wavelet  device, nsamp samples of dtype; borrowed until fd_clear_sources/fd_destroy.
+ *            Sample n enters the step that produces u^{n+1} (n counted from step 0),
+ *            scaled by amp * dt^2 / h^ndim; samples beyond nsamp are zero.
+ *   pos      host, (x, y, z) (z ignored in 2-D)
+ *   amp      multiplies the physical scaling; 1.0 is the paper's source.  Powers of two
+ *            keep FP32 values away from underflow and are exact.
+ * Fused into the stencil kernel.  Errors: FD_E_RANGE (position outside the grid or
+ * more than max_sources), FD_E_INVAL. */
+int fd_inject(fd_ctx *ctx, const void *wavelet, int64_t nsamp, const int64_t pos[3], double amp);
+int fd_clear_sources(fd_ctx *ctx);
+
+/* Record u^{n+1} at receiver positions after every step (fused into the stencil kernel).
+ *   pos     host, int32 [nrec][3] (x, y, z); z ignored in 2-D
+ *   traces  device, dtype, time-major [cap][nrec]; row i holds the step that starts
+ *           from step (k0 + i) where k0 is the context's step at this call; borrowed
+ *   nrec = 0 disables recording.  Replaces any previous receiver set.
+ * Errors: FD_E_RANGE (position outside, nrec > max_receivers), FD_E_INVAL. */
+int fd_record(fd_ctx *ctx, const int32_t *pos, int64_t nrec, void *traces, int64_t cap);
+
+/* Source samples of the Ricker wavelet s = (1 - 2 pi^2 f^2 tau^2) exp(-pi^2 f^2 tau^2),
+ * tau = n dt - t0 (Sec. 1 forcing), computed on the device.
+ *   out  device, nsamp values of dtype.  Enqueued on stream. */
+int fd_ricker(void *out, int64_t nsamp, double dt, double f0, double t0, fd_dtype dtype,
+              void *stream);
+
+/* ----------------------------------------------------------------- time stepping */
+
+/* Advance nsteps leapfrog steps (Sec. 1 time scheme), one stencil launch per step, with
+ * the sources added and the receivers recorded inside the launch.  nsteps = 0 is a no-op.
+ * Errors: FD_E_RANGE if recording is on and the trace capacity would be exceeded (checked
+ * before anything is enqueued), FD_E_STATE if poisoned. */
+int fd_step(fd_ctx *ctx, int64_t nsteps);
+
+/* Wait for the context's stream; reports asynchronous device errors (FD_E_DEVICE). */
+int fd_sync(fd_ctx *ctx);
+
+/* Current step count (number of steps taken since step 0 or the last fd_set_state). */
+int fd_get_step(const fd_ctx *ctx, int64_t *step);
+
+/* Copy the state (u^n, u^{n-1}) out of / into the context.
+ *   layout FD_DENSE: device dense arrays of dtype (fd_get_state packs, fd_set_state
+ *   unpacks and keeps the ghost cells zero); FD_PADDED: device buffers of
+ *   fd_field_bytes each, copied as they are (checkpoints).  Either pointer may be NULL to
+ *   skip that field.  fd_set_state also sets the step counter to `step`. */
+int fd_get_state(fd_ctx *ctx, void *u_cur, void *u_prev, int64_t *step, fd_layout layout);
+int fd_set_state(fd_ctx *ctx, const void *u_cur, const void *u_prev, int64_t step, fd_layout layout);
+
+/* One forward step from explicit padded buffers: out = 2 cur - prev + c L cur + sources at
+ * step index `step`; receivers are not recorded and the context's own state and step
+ * counter are untouched.  out may equal prev but not cur.  Used to recompute a checkpoint
+ * segment into a ring of padded fields for the adjoint. */
+int fd_step_explicit(fd_ctx *ctx, const void *cur, const void *prev, void *out, int64_t step);
+
+/* ----------------------------------------------------------------- adjoint (gradient) */
+
+/* Discrete adjoint of the forward scheme for J = 1/2 sum_n sum_j resid[n][j]^2 with
+ * resid = traces - observed (discretise, then differentiate; the paper's statement of
+ * the problem names full waveform inversion as the application, Sec. 1).  With
+ * c = (v dt / h)^2, mu = c lambda and mu^{T+1} = mu^{T+2} = 0, one call does, for
+ * k = k_hi .. k_lo+1 (descending):
+ *     mu^k = 2 mu^{k+1} - mu^{k+2} + c L^ mu^{k+1} + resid_amp sum_j c_j resid[k-1][j] e_j
+ *     g   += mu^k * (L^ u^{k-1})
+ * where L^ = h^2 L is the unscaled stencil.  dJ/dv = 2 g / v (fd_gradient_finish).
+ *   u_ckpt_cur, u_ckpt_prev  device padded u^{k_lo}, u^{k_lo - 1} (a forward checkpoint)
+ *   ring      device, (k_hi - k_lo - 1) padded fields; filled with u^{k_lo+1} ..
+ *             u^{k_hi-1} by recomputation from the checkpoint (may be NULL if
+ *             k_hi - k_lo == 1)
+ *   mu        device, 2 padded fields; mu^k lives in mu[k & 1]; both zero before the
+ *             first (highest) segment
+ *   resid     device [T][nrec] of dtype, rows indexed by step n (receivers as given to
+ *             fd_record)
+ *   grad      device padded field of dtype, accumulated (zero it before the first segment)
+ * Receivers must have been registered with fd_record (the traces buffer is not touched). */
+int fd_adjoint_segment(fd_ctx *ctx, const void *u_ckpt_cur, const void *u_ckpt_prev, int64_t k_lo,
+                       int64_t k_hi, void *ring, void *mu, const void *resid, double resid_amp,
+                       void *grad);
+
+/* dJ/dv = scale * 2 g / v on the dense grid.
+ *   grad_padded  device padded accumulator from fd_adjoint_segment
+ *   velocity     device dense v (dtype);  out: device dense dJ/dv (dtype) */
+int fd_gradient_finish(fd_ctx *ctx, const void *grad_padded, const void *velocity, void *out,
+                       double scale);
+
+/* ----------------------------------------------------------------- batched serving */
+
+/* Device bytes a batch of at most max_shots shots needs (shot table, workgroup prefix). */
+size_t fd_batch_workspace_bytes(int max_shots);
+
+/* A batch advances many same-(r, dtype, ndim) zero-boundary shots of different grid sizes
+ * in one stencil launch per step: each workgroup looks up its (shot, tile) from a prefix
+ * table, and each shot keeps its step counter in device memory, so a captured graph of
+ * an even number of steps can be replayed while shots come and go.
+ *   workspace  device, fd_batch_workspace_bytes(max_shots), borrowed until destroy */
+int fd_batch_create(fd_batch **out, int max_shots, void *workspace, size_t ws_bytes, void *stream);
+int fd_batch_destroy(fd_batch *b);
+
+/* Replace the member set.  Each context advances until its step reaches target[i] (host
+ * array); members keep their state and step.  Invalidates the captured graph. */
+int fd_batch_set(fd_batch *b, fd_ctx *const *ctxs, const int64_t *target, int nctx);
+
+/* Enqueue nsteps batched steps (nsteps even uses a captured graph chunk of that length;
+ * odd lengths fall back to direct launches).  Members already at their target do no work.
+ * Host step mirrors advance immediately; call fd_sync on a member (or the stream) to wait. */
+int fd_batch_step(fd_batch *b, int64_t nsteps);
+
+/* ----------------------------------------------------------------- measurement helpers */
+
+/* Plain device-to-device copy kernel (16-byte vectors, grid-stride) on stream: the
+ * attainable-bandwidth probe and the scale reference for hardware byte counters.
+ * bytes must be a multiple of 16 and both pointers 16-byte aligned. */
+int fd_copy_probe(void *dst, const void *src, size_t bytes, void *stream);
+
+/* Name of the stencil kernel configuration used for (dtype, r, ndim): tile shape,
+ * z-chunk and launch size. */
+const char *fd_kernel_config(const fd_ctx *ctx);
+
+/* Select a stencil tile configuration by index (0 = default) for contexts created
+ * afterwards with this (dtype, r, ndim); returns FD_E_RANGE for an unknown index.
+ * zchunk > 0 overrides the planes each workgroup marches in z. */
+int fd_set_tuning(fd_dtype dtype, int r, int ndim, int config, int zchunk);
+
+const char *fd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FDWAVE_H */

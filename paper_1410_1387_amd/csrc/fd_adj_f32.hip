@@ -1,0 +1,47 @@
+// fd_adj_f32.hip -- explicit instantiations of the adjoint stencil kernels for float
+// and the (radius, ndim) -> tile-configuration table the host side dispatches on.
+// The lists below are the tile shapes this file instantiates.
+#include "fd_stencil.h"
+
+namespace fdw {
+static const AdjEntry a3_r1 = adj_entry<TileCfg<float, 1, 3, 16, 16, 1>>("f32 r1 3d tile 64x16 (256 thr, 1 row/thr)");
+static const AdjEntry a2_r1 = adj_entry<TileCfg<float, 1, 2, 64, 1, 1>>("f32 r1 2d tile 256x1 (64 thr, 1 row/thr)");
+static const AdjEntry a3_r2 = adj_entry<TileCfg<float, 2, 3, 16, 16, 1>>("f32 r2 3d tile 64x16 (256 thr, 1 row/thr)");
+static const AdjEntry a2_r2 = adj_entry<TileCfg<float, 2, 2, 64, 1, 1>>("f32 r2 2d tile 256x1 (64 thr, 1 row/thr)");
+static const AdjEntry a3_r3 = adj_entry<TileCfg<float, 3, 3, 16, 16, 1>>("f32 r3 3d tile 64x16 (256 thr, 1 row/thr)");
+static const AdjEntry a2_r3 = adj_entry<TileCfg<float, 3, 2, 64, 1, 1>>("f32 r3 2d tile 256x1 (64 thr, 1 row/thr)");
+static const AdjEntry a3_r4 = adj_entry<TileCfg<float, 4, 3, 16, 16, 1>>("f32 r4 3d tile 64x16 (256 thr, 1 row/thr)");
+static const AdjEntry a2_r4 = adj_entry<TileCfg<float, 4, 2, 64, 1, 1>>("f32 r4 2d tile 256x1 (64 thr, 1 row/thr)");
+static const AdjEntry a3_r5 = adj_entry<TileCfg<float, 5, 3, 16, 16, 1>>("f32 r5 3d tile 64x16 (256 thr, 1 row/thr)");
+static const AdjEntry a2_r5 = adj_entry<TileCfg<float, 5, 2, 64, 1, 1>>("f32 r5 2d tile 256x1 (64 thr, 1 row/thr)");
+static const AdjEntry a3_r6 = adj_entry<TileCfg<float, 6, 3, 16, 16, 1>>("f32 r6 3d tile 64x16 (256 thr, 1 row/thr)");
+static const AdjEntry a2_r6 = adj_entry<TileCfg<float, 6, 2, 64, 1, 1>>("f32 r6 2d tile 256x1 (64 thr, 1 row/thr)");
+static const AdjEntry a3_r7 = adj_entry<TileCfg<float, 7, 3, 16, 16, 1>>("f32 r7 3d tile 64x16 (256 thr, 1 row/thr)");
+static const AdjEntry a2_r7 = adj_entry<TileCfg<float, 7, 2, 64, 1, 1>>("f32 r7 2d tile 256x1 (64 thr, 1 row/thr)");
+static const AdjEntry a3_r8 = adj_entry<TileCfg<float, 8, 3, 16, 16, 1>>("f32 r8 3d tile 64x16 (256 thr, 1 row/thr)");
+static const AdjEntry a2_r8 = adj_entry<TileCfg<float, 8, 2, 64, 1, 1>>("f32 r8 2d tile 256x1 (64 thr, 1 row/thr)");
+
+const AdjEntry *adj_config_f32(int r, int ndim)
+{
+    switch (r * 10 + ndim) {
+    case 12: return &a2_r1;
+    case 13: return &a3_r1;
+    case 22: return &a2_r2;
+    case 23: return &a3_r2;
+    case 32: return &a2_r3;
+    case 33: return &a3_r3;
+    case 42: return &a2_r4;
+    case 43: return &a3_r4;
+    case 52: return &a2_r5;
+    case 53: return &a3_r5;
+    case 62: return &a2_r6;
+    case 63: return &a3_r6;
+    case 72: return &a2_r7;
+    case 73: return &a3_r7;
+    case 82: return &a2_r8;
+    case 83: return &a3_r8;
+    default: return nullptr;
+    }
+}
+
+}  // namespace fdw

@@ -1,0 +1,904 @@
+// fd_api.hip -- host side of the C ABI declared in include/fdwave.h: argument
+// validation, the padded layout and workspace plan, the source/receiver event
+// tables, launch dispatch, state copies, the checkpointed adjoint driver and the
+// batched (graph-captured) serving step.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/fdwave.h"
+#include "fd_stencil.h"
+#include "fd_types.h"
+#include "fd_util.h"
+
+using namespace fdw;
+
+// ------------------------------------------------------------------ errors
+
+static thread_local std::string g_last_error;
+
+static int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+#define HIP_TRY(ctxp, expr)                                                                      \
+    do {                                                                                         \
+        hipError_t _e = (expr);                                                                  \
+        if (_e != hipSuccess) {                                                                  \
+            if (ctxp) (ctxp)->poisoned = true;                                                   \
+            return fail(FD_E_DEVICE, "%s: %s (%s:%d)", #expr, hipGetErrorString(_e), __FILE__, \
+                        __LINE__);                                                               \
+        }                                                                                        \
+    } while (0)
+
+extern "C" const char *fd_last_error(void) { return g_last_error.c_str(); }
+
+// ------------------------------------------------------------------ layout
+
+static inline int64_t align_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+
+namespace {
+
+struct Layout {
+    int ndim, r;
+    size_t esize;
+    int64_t knx, kny, knz;   // kernel-axis interior extent
+    int64_t px, py, planes;  // row pitch, rows per plane, planes
+    int64_t pxy, off0, elems;
+    size_t field_bytes;      // one padded field, rounded to 256 bytes
+    // workspace offsets
+    size_t o_desc, o_partial, o_minmax, o_buf0, o_buf1, o_c, o_evptr, o_ev, o_src, total;
+    int64_t ncol;
+};
+
+bool make_layout(const fd_grid *g, int r, fd_dtype dt, int64_t max_src, int64_t max_rec, Layout *L)
+{
+    if (!g || (g->ndim != 2 && g->ndim != 3) || r < 1 || r > 8) return false;
+    if (dt != FD_F32 && dt != FD_F64) return false;
+    for (int a = 0; a < 3; ++a)
+        if (g->n[a] < 1) return false;
+    if (g->ndim == 2 && g->n[2] != 1) return false;
+    if (max_src < 0 || max_rec < 0) return false;
+    L->ndim = g->ndim;
+    L->r = r;
+    L->esize = dt == FD_F32 ? 4 : 8;
+    const int64_t xo = 64 / (int64_t)L->esize;  // interior starts 64 bytes into each row
+    L->knx = g->n[0];
+    L->kny = g->ndim == 3 ? g->n[1] : 1;
+    L->knz = g->ndim == 3 ? g->n[2] : g->n[1];
+    if (L->knx > (1 << 30) || L->kny > (1 << 30) || L->knz > (1 << 30)) return false;
+    L->px = align_up(xo + align_up(L->knx, 256) + 16, 256 / (int64_t)L->esize);
+    L->py = g->ndim == 3 ? r + align_up(L->kny, 64) + r : 1;
+    L->planes = L->knz + 2 * r;
+    L->pxy = L->px * L->py;
+    L->off0 = (int64_t)r * L->pxy + (g->ndim == 3 ? (int64_t)r * L->px : 0) + xo;
+    L->elems = L->pxy * L->planes;
+    L->field_bytes = (size_t)align_up(L->elems * (int64_t)L->esize, 256);
+    L->ncol = L->knx * L->kny;
+    if (L->ncol + 1 > INT32_MAX || max_src + max_rec > INT32_MAX / 2) return false;
+    size_t o = 0;
+    L->o_desc = o;
+    o += align_up(sizeof(ShotDesc), 256);
+    L->o_partial = o;
+    o += align_up(2 * kPrepBlocks * sizeof(double), 256);
+    L->o_minmax = o;
+    o += 256;
+    L->o_buf0 = o;
+    o += L->field_bytes;
+    L->o_buf1 = o;
+    o += L->field_bytes;
+    L->o_c = o;
+    o += L->field_bytes;
+    L->o_evptr = o;
+    o += align_up((L->ncol + 1) * (int64_t)sizeof(int32_t), 256);
+    L->o_ev = o;
+    o += align_up(std::max<int64_t>(1, max_src + max_rec) * (int64_t)sizeof(Event), 256);
+    L->o_src = o;
+    o += align_up(std::max<int64_t>(1, max_src) * (int64_t)sizeof(SourceInfo), 256);
+    L->total = o;
+    return true;
+}
+
+Geom geom_of(const Layout &L)
+{
+    Geom g;
+    g.nx = L.knx;
+    g.ny = L.kny;
+    g.nz = L.knz;
+    g.px = L.px;
+    g.pxy = L.pxy;
+    g.off0 = L.off0;
+    return g;
+}
+
+// ------------------------------------------------------------------ kernel selection
+
+struct Tuning {
+    int config;
+    int zchunk;
+};
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int>, Tuning> g_tuning;
+
+const FwdEntry *fwd_table(fd_dtype dt, int r, int ndim, int *count)
+{
+    return dt == FD_F32 ? fwd_configs_f32(r, ndim, count) : fwd_configs_f64(r, ndim, count);
+}
+
+const AdjEntry *adj_table(fd_dtype dt, int r, int ndim)
+{
+    return dt == FD_F32 ? adj_config_f32(r, ndim) : adj_config_f64(r, ndim);
+}
+
+// Planes per z chunk: enough workgroups to fill 256 CUs several times over, but at
+// least 4r planes per chunk so the 2r-plane prologue stays a small overhead.
+int choose_zch(int64_t tiles_xy, int64_t nz, int r)
+{
+    const int64_t target_wgs = 2048;
+    int64_t chunks = (target_wgs + tiles_xy - 1) / tiles_xy;
+    chunks = std::min<int64_t>(chunks, std::max<int64_t>(1, nz / (4 * r)));
+    chunks = std::max<int64_t>(1, chunks);
+    return (int)((nz + chunks - 1) / chunks);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ context
+
+struct SourceRec {
+    int64_t pos[3];
+    const void *wav;
+    int64_t nsamp;
+    double amp;
+};
+
+struct fd_ctx {
+    fd_grid g;
+    int r;
+    double h, dt;
+    fd_dtype dtype;
+    fd_bc bc;
+    hipStream_t stream;
+    Layout L;
+    char *ws;
+    int64_t max_src, max_rec;
+    // kernels
+    const FwdEntry *kf;
+    const AdjEntry *ka;
+    int zch;
+    int64_t tiles_x, tiles_y, chunks_z, adj_chunks_z;
+    int adj_zch;
+    std::string cfg_name;
+    // host mirrors
+    ShotDesc desc;
+    std::vector<SourceRec> sources;
+    std::vector<int32_t> rec_pos;  // [nrec][3]
+    int64_t nrec;
+    void *traces;
+    int64_t rec_cap, rec_base;
+    std::vector<int32_t> h_evptr;
+    std::vector<Event> h_ev;
+    std::vector<SourceInfo> h_src;
+    int64_t step;
+    bool poisoned;
+    int xcd_remap;
+
+    void *buf(int i) const { return ws + (i == 0 ? L.o_buf0 : L.o_buf1); }
+    void *cfield() const { return ws + L.o_c; }
+    ShotDesc *d_desc() const { return reinterpret_cast<ShotDesc *>(ws + L.o_desc); }
+};
+
+static int check_ctx(const fd_ctx *c)
+{
+    if (!c) return fail(FD_E_INVAL, "null context");
+    if (c->poisoned) return fail(FD_E_STATE, "context is poisoned by an earlier device error");
+    return FD_OK;
+}
+
+// Rebuild the column-sorted event list and upload it together with the descriptor.
+static int upload_tables(fd_ctx *c)
+{
+    const Layout &L = c->L;
+    struct Tmp {
+        int64_t col;
+        int32_t z, code;
+    };
+    std::vector<Tmp> all;
+    all.reserve(c->sources.size() + (size_t)c->nrec);
+    auto colz = [&](const int64_t *p, int64_t *col, int32_t *z) {
+        if (L.ndim == 3) {
+            *col = p[1] * L.knx + p[0];
+            *z = (int32_t)p[2];
+        } else {
+            *col = p[0];
+            *z = (int32_t)p[1];
+        }
+    };
+    c->h_src.clear();
+    for (size_t s = 0; s < c->sources.size(); ++s) {
+        const SourceRec &sr = c->sources[s];
+        Tmp t;
+        colz(sr.pos, &t.col, &t.z);
+        t.code = ~(int32_t)s;
+        all.push_back(t);
+        SourceInfo si;
+        si.wav = sr.wav;
+        si.nsamp = sr.nsamp;
+        si.scale = sr.amp * c->dt * c->dt / std::pow(c->h, (double)L.ndim);
+        c->h_src.push_back(si);
+    }
+    for (int64_t j = 0; j < c->nrec; ++j) {
+        int64_t p[3] = {c->rec_pos[3 * j], c->rec_pos[3 * j + 1], c->rec_pos[3 * j + 2]};
+        Tmp t;
+        colz(p, &t.col, &t.z);
+        t.code = (int32_t)j;
+        all.push_back(t);
+    }
+    // sources sort before receivers at the same point (negative codes first)
+    std::sort(all.begin(), all.end(), [](const Tmp &a, const Tmp &b) {
+        if (a.col != b.col) return a.col < b.col;
+        if (a.z != b.z) return a.z < b.z;
+        return a.code < b.code;
+    });
+    c->h_ev.resize(all.size());
+    c->h_evptr.assign((size_t)L.ncol + 1, 0);
+    for (size_t i = 0; i < all.size(); ++i) {
+        c->h_ev[i].z = all[i].z;
+        c->h_ev[i].code = all[i].code;
+        c->h_evptr[(size_t)all[i].col + 1]++;
+    }
+    for (int64_t i = 0; i < L.ncol; ++i) c->h_evptr[(size_t)i + 1] += c->h_evptr[(size_t)i];
+
+    ShotDesc &d = c->desc;
+    const bool any = !all.empty();
+    d.ev_ptr = any ? reinterpret_cast<const int32_t *>(c->ws + L.o_evptr) : nullptr;
+    d.ev = reinterpret_cast<const Event *>(c->ws + L.o_ev);
+    d.src = reinterpret_cast<const SourceInfo *>(c->ws + L.o_src);
+    d.traces = c->traces;
+    d.nrec = c->nrec;
+    d.rec_base = c->rec_base;
+    d.rec_cap = c->rec_cap;
+    if (any) {
+        HIP_TRY(c, hipMemcpyAsync(c->ws + L.o_evptr, c->h_evptr.data(), c->h_evptr.size() * sizeof(int32_t),
+                                  hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(c, hipMemcpyAsync(c->ws + L.o_ev, c->h_ev.data(), c->h_ev.size() * sizeof(Event),
+                                  hipMemcpyHostToDevice, c->stream));
+        if (!c->h_src.empty())
+            HIP_TRY(c, hipMemcpyAsync(c->ws + L.o_src, c->h_src.data(), c->h_src.size() * sizeof(SourceInfo),
+                                      hipMemcpyHostToDevice, c->stream));
+    }
+    HIP_TRY(c, hipMemcpyAsync(c->d_desc(), &c->desc, sizeof(ShotDesc), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return FD_OK;
+}
+
+// ------------------------------------------------------------------ stencil, limits, planning
+
+extern "C" int fd_weights(int r, double *w)
+{
+    if (r < 1 || r > 8 || !w) return fail(FD_E_INVAL, "fd_weights: r must be in [1, 8]");
+    double s = 0.0;
+    for (int l = 1; l <= r; ++l) {
+        w[l] = stencil_weight(r, l);
+        s += w[l];
+    }
+    w[0] = -2.0 * s;
+    return FD_OK;
+}
+
+extern "C" double fd_dt_max(int ndim, int r, double h, double vmax)
+{
+    if (ndim < 1 || ndim > 3 || r < 1 || r > 8 || !(h > 0) || !(vmax > 0)) return -1.0;
+    // S_r = -w0 + 2 sum |w_l|: the 1-D symbol at theta = pi, where it is largest
+    double w[9];
+    fd_weights(r, w);
+    double S = -w[0];
+    for (int l = 1; l <= r; ++l) S += 2.0 * std::fabs(w[l]);
+    return 2.0 * h / (vmax * std::sqrt((double)ndim * S));
+}
+
+extern "C" int fd_field_bytes(const fd_grid *g, int r, fd_dtype dtype, size_t *bytes)
+{
+    Layout L;
+    if (!bytes || !make_layout(g, r, dtype, 0, 0, &L)) return fail(FD_E_INVAL, "fd_field_bytes: bad grid/r/dtype");
+    *bytes = L.field_bytes;
+    return FD_OK;
+}
+
+extern "C" int fd_workspace_bytes(const fd_grid *g, int r, fd_dtype dtype, int64_t max_sources,
+                                  int64_t max_receivers, size_t *bytes)
+{
+    Layout L;
+    if (!bytes || !make_layout(g, r, dtype, max_sources, max_receivers, &L))
+        return fail(FD_E_INVAL, "fd_workspace_bytes: bad grid/r/dtype/maxima");
+    *bytes = L.total;
+    return FD_OK;
+}
+
+extern "C" int fd_set_tuning(fd_dtype dtype, int r, int ndim, int config, int zchunk)
+{
+    int count = 0;
+    if ((dtype != FD_F32 && dtype != FD_F64) || r < 1 || r > 8 || (ndim != 2 && ndim != 3))
+        return fail(FD_E_INVAL, "fd_set_tuning: bad dtype/r/ndim");
+    fwd_table(dtype, r, ndim, &count);
+    if (config < 0 || config >= count) return fail(FD_E_RANGE, "fd_set_tuning: config %d of %d", config, count);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuning[std::make_tuple((int)dtype, r, ndim)] = Tuning{config, zchunk};
+    return FD_OK;
+}
+
+// ------------------------------------------------------------------ lifecycle
+
+extern "C" int fd_create(fd_ctx **out, const fd_grid *g, int r, double h, double dt, const void *velocity,
+                         fd_dtype dtype, fd_bc bc, void *workspace, size_t ws_bytes, int64_t max_sources,
+                         int64_t max_receivers, void *stream)
+{
+    if (!out) return fail(FD_E_INVAL, "fd_create: null out");
+    *out = nullptr;
+    Layout L;
+    if (!make_layout(g, r, dtype, max_sources, max_receivers, &L))
+        return fail(FD_E_INVAL, "fd_create: bad grid (ndim 2/3, n >= 1, nz = 1 in 2-D), r in [1,8], dtype or maxima");
+    if (!(h > 0) || !(dt > 0) || !std::isfinite(h) || !std::isfinite(dt))
+        return fail(FD_E_INVAL, "fd_create: h and dt must be positive");
+    if (bc != FD_BC_ZERO && bc != FD_BC_PERIODIC) return fail(FD_E_INVAL, "fd_create: bad boundary");
+    if (!velocity || !workspace) return fail(FD_E_INVAL, "fd_create: null velocity or workspace");
+    if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return fail(FD_E_INVAL, "fd_create: workspace not 256-byte aligned");
+    if (ws_bytes < L.total)
+        return fail(FD_E_NOMEM, "fd_create: workspace %zu bytes < %zu needed", ws_bytes, L.total);
+    if (bc == FD_BC_PERIODIC) {
+        const int64_t ext[3] = {L.knx, L.kny, L.knz};
+        for (int a = 0; a < 3; ++a)
+            if ((a != 1 || L.ndim == 3) && ext[a] < r)
+                return fail(FD_E_INVAL, "fd_create: periodic grid must have at least r points per axis");
+    }
+
+    int count = 0;
+    const FwdEntry *tab = fwd_table(dtype, r, g->ndim, &count);
+    const AdjEntry *ka = adj_table(dtype, r, g->ndim);
+    if (!tab || count == 0 || !ka) return fail(FD_E_INVAL, "fd_create: no kernel for this dtype/r/ndim");
+    Tuning tu{0, 0};
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tuning.find(std::make_tuple((int)dtype, r, (int)g->ndim));
+        if (it != g_tuning.end()) tu = it->second;
+    }
+
+    fd_ctx *c = new fd_ctx();
+    c->g = *g;
+    c->r = r;
+    c->h = h;
+    c->dt = dt;
+    c->dtype = dtype;
+    c->bc = bc;
+    c->stream = (hipStream_t)stream;
+    c->L = L;
+    c->ws = (char *)workspace;
+    c->max_src = max_sources;
+    c->max_rec = max_receivers;
+    c->kf = &tab[tu.config];
+    c->ka = ka;
+    c->tiles_x = (L.knx + c->kf->bx - 1) / c->kf->bx;
+    c->tiles_y = (L.kny + c->kf->by - 1) / c->kf->by;
+    c->zch = tu.zchunk > 0 ? (int)std::min<int64_t>(tu.zchunk, L.knz) : choose_zch(c->tiles_x * c->tiles_y, L.knz, r);
+    c->chunks_z = (L.knz + c->zch - 1) / c->zch;
+    c->nrec = 0;
+    c->traces = nullptr;
+    c->rec_cap = 0;
+    c->rec_base = 0;
+    c->step = 0;
+    c->poisoned = false;
+    c->xcd_remap = 1;
+    char nm[256];
+    snprintf(nm, sizeof(nm), "%s, zchunk %d, grid %lld wg", c->kf->name, c->zch,
+             (long long)(c->tiles_x * c->tiles_y * c->chunks_z));
+    c->cfg_name = nm;
+
+    // zero the workspace: both wavefields (u^0 = u^-1 = 0), c ghosts, tables
+    hipError_t e = hipMemsetAsync(workspace, 0, L.total, c->stream);
+    if (e == hipSuccess) {
+        const double k = (dt / h) * (dt / h);
+        e = launch_prep((int)dtype, geom_of(L), velocity, c->cfield(), k, (double *)(c->ws + L.o_partial),
+                        (double *)(c->ws + L.o_minmax), c->stream);
+    }
+    double mm[2] = {0, 0};
+    if (e == hipSuccess) e = hipMemcpyAsync(mm, c->ws + L.o_minmax, sizeof(mm), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        delete c;
+        return fail(FD_E_DEVICE, "fd_create: %s", hipGetErrorString(e));
+    }
+    if (!(mm[0] > 0) || !std::isfinite(mm[1])) {
+        delete c;
+        return fail(FD_E_INVAL, "fd_create: velocity must be finite and positive (min %g, max %g)", mm[0], mm[1]);
+    }
+    const double dtm = fd_dt_max(g->ndim, r, h, mm[1]);
+    if (dt > dtm) {
+        delete c;
+        return fail(FD_E_UNSTABLE, "fd_create: dt %.6g exceeds the stability limit %.6g for vmax %.6g", dt, dtm, mm[1]);
+    }
+
+    ShotDesc &d = c->desc;
+    std::memset(&d, 0, sizeof(d));
+    d.buf[0] = c->buf(0);
+    d.buf[1] = c->buf(1);
+    d.c = c->cfield();
+    d.nx = (int32_t)L.knx;
+    d.ny = (int32_t)L.kny;
+    d.nz = (int32_t)L.knz;
+    d.tiles_x = (int32_t)c->tiles_x;
+    d.tiles_y = (int32_t)c->tiles_y;
+    d.chunks_z = (int32_t)c->chunks_z;
+    d.zch = c->zch;
+    d.px = L.px;
+    d.pxy = L.pxy;
+    d.off0 = L.off0;
+    d.ctr[0] = 0;
+    d.ctr[1] = 0;
+    d.target = 0;
+    int st = upload_tables(c);
+    if (st != FD_OK) {
+        delete c;
+        return st;
+    }
+    *out = c;
+    return FD_OK;
+}
+
+extern "C" int fd_destroy(fd_ctx *ctx)
+{
+    if (!ctx) return fail(FD_E_INVAL, "fd_destroy: null context");
+    if (!ctx->poisoned) (void)hipStreamSynchronize(ctx->stream);
+    delete ctx;
+    return FD_OK;
+}
+
+extern "C" int fd_set_stream(fd_ctx *ctx, void *stream)
+{
+    int st = check_ctx(ctx);
+    if (st) return st;
+    ctx->stream = (hipStream_t)stream;
+    return FD_OK;
+}
+
+extern "C" const char *fd_kernel_config(const fd_ctx *ctx) { return ctx ? ctx->cfg_name.c_str() : ""; }
+
+// ------------------------------------------------------------------ sources and receivers
+
+static bool in_grid(const fd_ctx *c, const int64_t *p)
+{
+    const int nd = c->L.ndim;
+    for (int a = 0; a < nd; ++a)
+        if (p[a] < 0 || p[a] >= c->g.n[a]) return false;
+    return true;
+}
+
+extern "C" int fd_inject(fd_ctx *ctx, const void *wavelet, int64_t nsamp, const int64_t pos[3], double amp)
+{
+    int st = check_ctx(ctx);
+    if (st) return st;
+    if (!pos || nsamp < 0 || (nsamp > 0 && !wavelet) || !std::isfinite(amp))
+        return fail(FD_E_INVAL, "fd_inject: bad wavelet, nsamp or amp");
+    int64_t p[3] = {pos[0], pos[1], ctx->L.ndim == 3 ? pos[2] : 0};
+    if (!in_grid(ctx, p)) return fail(FD_E_RANGE, "fd_inject: position (%lld, %lld, %lld) outside the grid",
+                                      (long long)p[0], (long long)p[1], (long long)p[2]);
+    if ((int64_t)ctx->sources.size() >= ctx->max_src)
+        return fail(FD_E_RANGE, "fd_inject: more than max_sources = %lld", (long long)ctx->max_src);
+    SourceRec sr;
+    std::memcpy(sr.pos, p, sizeof(p));
+    sr.wav = wavelet;
+    sr.nsamp = nsamp;
+    sr.amp = amp;
+    ctx->sources.push_back(sr);
+    return upload_tables(ctx);
+}
+
+extern "C" int fd_clear_sources(fd_ctx *ctx)
+{
+    int st = check_ctx(ctx);
+    if (st) return st;
+    ctx->sources.clear();
+    return upload_tables(ctx);
+}
+
+extern "C" int fd_record(fd_ctx *ctx, const int32_t *pos, int64_t nrec, void *traces, int64_t cap)
+{
+    int st = check_ctx(ctx);
+    if (st) return st;
+    if (nrec < 0 || (nrec > 0 && (!pos || !traces || cap < 0)))
+        return fail(FD_E_INVAL, "fd_record: bad receiver arguments");
+    if (nrec > ctx->max_rec)
+        return fail(FD_E_RANGE, "fd_record: %lld receivers > max_receivers = %lld", (long long)nrec, (long long)ctx->max_rec);
+    std::vector<int32_t> rp((size_t)nrec * 3);
+    for (int64_t j = 0; j < nrec; ++j) {
+        int64_t p[3] = {pos[3 * j], pos[3 * j + 1], ctx->L.ndim == 3 ? pos[3 * j + 2] : 0};
+        if (!in_grid(ctx, p)) return fail(FD_E_RANGE, "fd_record: receiver %lld outside the grid", (long long)j);
+        rp[3 * j] = (int32_t)p[0];
+        rp[3 * j + 1] = (int32_t)p[1];
+        rp[3 * j + 2] = (int32_t)p[2];
+    }
+    ctx->rec_pos.swap(rp);
+    ctx->nrec = nrec;
+    ctx->traces = nrec > 0 ? traces : nullptr;
+    ctx->rec_cap = nrec > 0 ? cap : 0;
+    ctx->rec_base = ctx->step;
+    return upload_tables(ctx);
+}
+
+extern "C" int fd_ricker(void *out, int64_t nsamp, double dt, double f0, double t0, fd_dtype dtype, void *stream)
+{
+    if (nsamp < 0 || (nsamp > 0 && !out) || !(dt > 0) || !(f0 > 0) || (dtype != FD_F32 && dtype != FD_F64))
+        return fail(FD_E_INVAL, "fd_ricker: bad arguments");
+    hipError_t e = launch_ricker((int)dtype, out, nsamp, dt, f0, t0, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(FD_E_DEVICE, "fd_ricker: %s", hipGetErrorString(e));
+    return FD_OK;
+}
+
+// ------------------------------------------------------------------ stepping
+
+static LaunchArgs direct_args(const fd_ctx *c, int64_t step)
+{
+    LaunchArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.shots = c->d_desc();
+    a.wg_prefix = nullptr;
+    a.nshots = 1;
+    a.slot = 0;
+    a.step = step;
+    a.record = 1;
+    a.xcd_remap = c->xcd_remap;
+    return a;
+}
+
+static int64_t nwg_of(const fd_ctx *c) { return c->tiles_x * c->tiles_y * c->chunks_z; }
+
+extern "C" int fd_step(fd_ctx *ctx, int64_t nsteps)
+{
+    int st = check_ctx(ctx);
+    if (st) return st;
+    if (nsteps < 0) return fail(FD_E_INVAL, "fd_step: negative nsteps");
+    if (nsteps == 0) return FD_OK;
+    if (ctx->nrec > 0 && ctx->step + nsteps - ctx->rec_base > ctx->rec_cap)
+        return fail(FD_E_RANGE, "fd_step: trace capacity %lld exceeded (step %lld + %lld, recording from %lld)",
+                    (long long)ctx->rec_cap, (long long)ctx->step, (long long)nsteps, (long long)ctx->rec_base);
+    const int64_t nwg = nwg_of(ctx);
+    const Geom gm = geom_of(ctx->L);
+    for (int64_t i = 0; i < nsteps; ++i) {
+        if (ctx->bc == FD_BC_PERIODIC)
+            HIP_TRY(ctx, launch_halo_periodic((int)ctx->dtype, gm, ctx->r, ctx->L.ndim == 3 ? ctx->r : 0, ctx->r,
+                                              ctx->buf((int)(ctx->step & 1)), ctx->stream));
+        LaunchArgs a = direct_args(ctx, ctx->step);
+        ctx->kf->launch(a, (int)nwg, ctx->stream);
+        HIP_TRY(ctx, hipGetLastError());
+        ctx->step++;
+    }
+    return FD_OK;
+}
+
+extern "C" int fd_sync(fd_ctx *ctx)
+{
+    if (!ctx) return fail(FD_E_INVAL, "fd_sync: null context");
+    if (ctx->poisoned) return fail(FD_E_STATE, "context is poisoned");
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    HIP_TRY(ctx, hipGetLastError());
+    return FD_OK;
+}
+
+extern "C" int fd_get_step(const fd_ctx *ctx, int64_t *step)
+{
+    if (!ctx || !step) return fail(FD_E_INVAL, "fd_get_step: null argument");
+    *step = ctx->step;
+    return FD_OK;
+}
+
+extern "C" int fd_get_state(fd_ctx *ctx, void *u_cur, void *u_prev, int64_t *step, fd_layout layout)
+{
+    int st = check_ctx(ctx);
+    if (st) return st;
+    if (layout != FD_DENSE && layout != FD_PADDED) return fail(FD_E_INVAL, "fd_get_state: bad layout");
+    void *dst[2] = {u_cur, u_prev};
+    const int src[2] = {(int)(ctx->step & 1), (int)((ctx->step + 1) & 1)};
+    for (int i = 0; i < 2; ++i) {
+        if (!dst[i]) continue;
+        if (layout == FD_PADDED)
+            HIP_TRY(ctx, hipMemcpyAsync(dst[i], ctx->buf(src[i]), ctx->L.field_bytes, hipMemcpyDeviceToDevice, ctx->stream));
+        else
+            HIP_TRY(ctx, launch_pack((int)ctx->dtype, geom_of(ctx->L), ctx->buf(src[i]), dst[i], ctx->stream));
+    }
+    if (step) *step = ctx->step;
+    return FD_OK;
+}
+
+extern "C" int fd_set_state(fd_ctx *ctx, const void *u_cur, const void *u_prev, int64_t step, fd_layout layout)
+{
+    int st = check_ctx(ctx);
+    if (st) return st;
+    if (layout != FD_DENSE && layout != FD_PADDED) return fail(FD_E_INVAL, "fd_set_state: bad layout");
+    if (step < 0) return fail(FD_E_INVAL, "fd_set_state: negative step");
+    const void *srcp[2] = {u_cur, u_prev};
+    const int dst[2] = {(int)(step & 1), (int)((step + 1) & 1)};
+    // a new step parity may move the roles of the two buffers: copy both before use
+    for (int i = 0; i < 2; ++i) {
+        if (!srcp[i]) continue;
+        if (layout == FD_PADDED)
+            HIP_TRY(ctx, hipMemcpyAsync(ctx->buf(dst[i]), srcp[i], ctx->L.field_bytes, hipMemcpyDeviceToDevice, ctx->stream));
+        else
+            HIP_TRY(ctx, launch_unpack((int)ctx->dtype, geom_of(ctx->L), srcp[i], ctx->buf(dst[i]), ctx->stream));
+    }
+    ctx->step = step;
+    return FD_OK;
+}
+
+extern "C" int fd_step_explicit(fd_ctx *ctx, const void *cur, const void *prev, void *out, int64_t step)
+{
+    int st = check_ctx(ctx);
+    if (st) return st;
+    if (!cur || !prev || !out || step < 0) return fail(FD_E_INVAL, "fd_step_explicit: bad arguments");
+    if (out == cur) return fail(FD_E_INVAL, "fd_step_explicit: out must not alias cur");
+    if (ctx->bc != FD_BC_ZERO) return fail(FD_E_STATE, "fd_step_explicit: zero boundary only");
+    LaunchArgs a = direct_args(ctx, step);
+    a.cur = cur;
+    a.prev = prev;
+    a.out = out;
+    a.record = 0;
+    ctx->kf->launch(a, (int)nwg_of(ctx), ctx->stream);
+    HIP_TRY(ctx, hipGetLastError());
+    return FD_OK;
+}
+
+// ------------------------------------------------------------------ adjoint
+
+extern "C" int fd_adjoint_segment(fd_ctx *ctx, const void *u_ckpt_cur, const void *u_ckpt_prev, int64_t k_lo,
+                                  int64_t k_hi, void *ring, void *mu, const void *resid, double resid_amp, void *grad)
+{
+    int st = check_ctx(ctx);
+    if (st) return st;
+    if (ctx->bc != FD_BC_ZERO) return fail(FD_E_STATE, "fd_adjoint_segment: zero boundary only");
+    const int64_t nk = k_hi - k_lo;
+    if (k_lo < 0 || nk < 1 || !u_ckpt_cur || !u_ckpt_prev || !mu || !grad || (nk > 1 && !ring))
+        return fail(FD_E_INVAL, "fd_adjoint_segment: bad arguments");
+    if (ctx->nrec > 0 && !resid) return fail(FD_E_INVAL, "fd_adjoint_segment: null residual");
+    const size_t fb = ctx->L.field_bytes;
+    auto slot = [&](int64_t i) -> void * {  // u^{k_lo + i}
+        return i == 0 ? const_cast<void *>(u_ckpt_cur) : (char *)ring + (size_t)(i - 1) * fb;
+    };
+    // recompute u^{k_lo+1} .. u^{k_hi-1} from the checkpoint into the ring
+    for (int64_t i = 1; i < nk; ++i) {
+        const void *prev = (i == 1) ? u_ckpt_prev : slot(i - 2);
+        int s2 = fd_step_explicit(ctx, slot(i - 1), prev, slot(i), k_lo + i - 1);
+        if (s2) return s2;
+    }
+    // adjoint steps k = k_hi .. k_lo + 1
+    void *m[2] = {mu, (char *)mu + fb};
+    const int64_t nwg = ctx->tiles_x * ctx->tiles_y * ctx->chunks_z;
+    for (int64_t k = k_hi; k > k_lo; --k) {
+        AdjArgs a;
+        std::memset(&a, 0, sizeof(a));
+        a.shot = ctx->d_desc();
+        a.mu_cur = m[(k + 1) & 1];
+        a.mu_out = m[k & 1];
+        a.u_km1 = slot(k - 1 - k_lo);
+        a.grad = grad;
+        a.resid = resid;
+        a.k = k;
+        a.resid_amp = resid_amp;
+        a.xcd_remap = ctx->xcd_remap;
+        ctx->ka->launch(a, (int)nwg, ctx->stream);
+        HIP_TRY(ctx, hipGetLastError());
+    }
+    return FD_OK;
+}
+
+extern "C" int fd_gradient_finish(fd_ctx *ctx, const void *grad_padded, const void *velocity, void *out, double scale)
+{
+    int st = check_ctx(ctx);
+    if (st) return st;
+    if (!grad_padded || !velocity || !out) return fail(FD_E_INVAL, "fd_gradient_finish: null pointer");
+    HIP_TRY(ctx, launch_grad_finish((int)ctx->dtype, geom_of(ctx->L), grad_padded, velocity, out, scale, ctx->stream));
+    return FD_OK;
+}
+
+// ------------------------------------------------------------------ batched serving
+
+struct fd_batch {
+    int max_shots;
+    char *ws;
+    hipStream_t stream;
+    hipStream_t cap_stream;
+    std::vector<fd_ctx *> members;
+    std::vector<int64_t> target;
+    std::vector<ShotDesc> h_desc;
+    std::vector<int32_t> h_prefix;
+    int64_t nwg;
+    int slot;
+    const FwdEntry *kf;
+    hipGraphExec_t exec;
+    int64_t exec_len;
+    bool has_exec;
+
+    ShotDesc *d_desc() const { return reinterpret_cast<ShotDesc *>(ws); }
+    int32_t *d_prefix() const { return reinterpret_cast<int32_t *>(ws + align_up((int64_t)max_shots * sizeof(ShotDesc), 256)); }
+};
+
+extern "C" size_t fd_batch_workspace_bytes(int max_shots)
+{
+    if (max_shots < 1) return 0;
+    return (size_t)align_up((int64_t)max_shots * sizeof(ShotDesc), 256) +
+           (size_t)align_up((int64_t)(max_shots + 1) * sizeof(int32_t), 256);
+}
+
+extern "C" int fd_batch_create(fd_batch **out, int max_shots, void *workspace, size_t ws_bytes, void *stream)
+{
+    if (!out || max_shots < 1 || !workspace) return fail(FD_E_INVAL, "fd_batch_create: bad arguments");
+    if (ws_bytes < fd_batch_workspace_bytes(max_shots)) return fail(FD_E_NOMEM, "fd_batch_create: workspace too small");
+    fd_batch *b = new fd_batch();
+    b->max_shots = max_shots;
+    b->ws = (char *)workspace;
+    b->stream = (hipStream_t)stream;
+    b->nwg = 0;
+    b->slot = 0;
+    b->kf = nullptr;
+    b->has_exec = false;
+    b->exec_len = 0;
+    hipError_t e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        delete b;
+        return fail(FD_E_DEVICE, "fd_batch_create: %s", hipGetErrorString(e));
+    }
+    *out = b;
+    return FD_OK;
+}
+
+static void batch_drop_graph(fd_batch *b)
+{
+    if (b->has_exec) {
+        (void)hipGraphExecDestroy(b->exec);
+        b->has_exec = false;
+    }
+}
+
+extern "C" int fd_batch_destroy(fd_batch *b)
+{
+    if (!b) return fail(FD_E_INVAL, "fd_batch_destroy: null batch");
+    (void)hipStreamSynchronize(b->stream);
+    batch_drop_graph(b);
+    (void)hipStreamDestroy(b->cap_stream);
+    delete b;
+    return FD_OK;
+}
+
+extern "C" int fd_batch_set(fd_batch *b, fd_ctx *const *ctxs, const int64_t *target, int nctx)
+{
+    if (!b || nctx < 0 || nctx > b->max_shots || (nctx > 0 && (!ctxs || !target)))
+        return fail(FD_E_INVAL, "fd_batch_set: bad arguments");
+    const FwdEntry *kf = nullptr;
+    for (int i = 0; i < nctx; ++i) {
+        fd_ctx *c = ctxs[i];
+        int st = check_ctx(c);
+        if (st) return st;
+        if (c->bc != FD_BC_ZERO) return fail(FD_E_INVAL, "fd_batch_set: member %d is not zero-boundary", i);
+        if (!kf) kf = c->kf;
+        if (c->kf != kf) return fail(FD_E_INVAL, "fd_batch_set: member %d uses another kernel (r/dtype/ndim/tile)", i);
+        if (target[i] < c->step) return fail(FD_E_INVAL, "fd_batch_set: target below the member's step");
+        if (c->nrec > 0 && target[i] - c->rec_base > c->rec_cap)
+            return fail(FD_E_RANGE, "fd_batch_set: member %d target exceeds its trace capacity", i);
+    }
+    // wait for earlier batched work before rewriting the shot table it reads
+    hipError_t e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return fail(FD_E_DEVICE, "fd_batch_set: %s", hipGetErrorString(e));
+    batch_drop_graph(b);
+    b->members.assign(ctxs, ctxs + nctx);
+    b->target.assign(target, target + nctx);
+    b->h_desc.resize((size_t)nctx);
+    b->h_prefix.assign((size_t)nctx + 1, 0);
+    for (int i = 0; i < nctx; ++i) {
+        fd_ctx *c = ctxs[i];
+        ShotDesc d = c->desc;
+        d.ctr[0] = c->step;
+        d.ctr[1] = c->step;
+        d.target = target[i];
+        b->h_desc[(size_t)i] = d;
+        b->h_prefix[(size_t)i + 1] = b->h_prefix[(size_t)i] + (int32_t)nwg_of(c);
+    }
+    b->nwg = b->h_prefix[(size_t)nctx];
+    b->kf = kf;
+    b->slot = 0;
+    if (nctx > 0) {
+        e = hipMemcpyAsync(b->d_desc(), b->h_desc.data(), (size_t)nctx * sizeof(ShotDesc), hipMemcpyHostToDevice, b->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(b->d_prefix(), b->h_prefix.data(), b->h_prefix.size() * sizeof(int32_t),
+                               hipMemcpyHostToDevice, b->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+        if (e != hipSuccess) return fail(FD_E_DEVICE, "fd_batch_set: %s", hipGetErrorString(e));
+    }
+    return FD_OK;
+}
+
+static LaunchArgs batch_args(const fd_batch *b, int slot)
+{
+    LaunchArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.shots = b->d_desc();
+    a.wg_prefix = b->members.size() > 1 ? b->d_prefix() : nullptr;
+    a.nshots = (int32_t)b->members.size();
+    a.slot = slot;
+    a.step = -1;
+    a.record = 1;
+    a.xcd_remap = 1;
+    return a;
+}
+
+extern "C" int fd_batch_step(fd_batch *b, int64_t nsteps)
+{
+    if (!b || nsteps < 0) return fail(FD_E_INVAL, "fd_batch_step: bad arguments");
+    if (b->members.empty() || nsteps == 0) return FD_OK;
+    int64_t done = 0;
+    // align to slot 0 with a direct launch, then replay the captured even-length chunk
+    while (done < nsteps && (b->slot != 0 || nsteps - done < 2)) {
+        b->kf->launch(batch_args(b, b->slot), (int)b->nwg, b->stream);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return fail(FD_E_DEVICE, "fd_batch_step: %s", hipGetErrorString(e));
+        b->slot ^= 1;
+        ++done;
+    }
+    const int64_t rest = nsteps - done;
+    const int64_t chunk = rest - (rest & 1);
+    if (chunk > 0) {
+        if (!b->has_exec || b->exec_len != chunk) {
+            batch_drop_graph(b);
+            hipGraph_t graph;
+            hipError_t e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) return fail(FD_E_DEVICE, "fd_batch_step: capture: %s", hipGetErrorString(e));
+            for (int64_t i = 0; i < chunk; ++i) b->kf->launch(batch_args(b, (int)(i & 1)), (int)b->nwg, b->cap_stream);
+            e = hipStreamEndCapture(b->cap_stream, &graph);
+            if (e != hipSuccess) return fail(FD_E_DEVICE, "fd_batch_step: end capture: %s", hipGetErrorString(e));
+            e = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (e != hipSuccess) return fail(FD_E_DEVICE, "fd_batch_step: instantiate: %s", hipGetErrorString(e));
+            b->has_exec = true;
+            b->exec_len = chunk;
+        }
+        hipError_t e = hipGraphLaunch(b->exec, b->stream);
+        if (e != hipSuccess) return fail(FD_E_DEVICE, "fd_batch_step: graph launch: %s", hipGetErrorString(e));
+        done += chunk;
+    }
+    // an odd tail
+    while (done < nsteps) {
+        b->kf->launch(batch_args(b, b->slot), (int)b->nwg, b->stream);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return fail(FD_E_DEVICE, "fd_batch_step: %s", hipGetErrorString(e));
+        b->slot ^= 1;
+        ++done;
+    }
+    for (size_t i = 0; i < b->members.size(); ++i) {
+        fd_ctx *c = b->members[i];
+        c->step = std::min(c->step + nsteps, b->target[i]);
+    }
+    return FD_OK;
+}
+
+// ------------------------------------------------------------------ measurement helpers
+
+extern "C" int fd_copy_probe(void *dst, const void *src, size_t bytes, void *stream)
+{
+    if (!dst || !src || bytes % 16 != 0 || reinterpret_cast<uintptr_t>(dst) % 16 || reinterpret_cast<uintptr_t>(src) % 16)
+        return fail(FD_E_INVAL, "fd_copy_probe: bad arguments");
+    hipError_t e = launch_copy_probe(dst, src, bytes, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(FD_E_DEVICE, "fd_copy_probe: %s", hipGetErrorString(e));
+    return FD_OK;
+}

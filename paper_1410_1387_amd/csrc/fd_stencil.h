@@ -1,0 +1,808 @@
+// fd_stencil.h -- gfx950 stencil kernels for the leapfrog acoustic update.
+//
+// One launch performs one time step of
+//     u^{n+1} = 2 u^n - u^{n-1} + c * Lh u^n + sources,   c = (v dt / h)^2,
+// where Lh = h^2 L is the radius-R star stencil applied on every axis (the xy
+// stencil form of Sec. 1 of Medina, St-Cyr and Warburton, extended to z with
+// the same radius and spacing).  It is evaluated in difference form,
+//     Lh u = sum_axes sum_l w_l [ (u_{+l} - u) + (u_{-l} - u) ],
+// which is algebraically the centre-weight form and keeps FP32 rounding of
+// smooth fields small.
+//
+// Design (a star stencil is not a dense contraction, so no MFMA):
+//  - A workgroup owns a BX x BY tile of the xy plane and marches a chunk of z
+//    planes.  Each thread owns VEC consecutive x points (one 16-byte vector) in
+//    EY rows and keeps u^n of its column at planes z-R..z+R in registers (the
+//    z "register queue"); the plane z with an R-wide x/y halo is staged in LDS
+//    (double buffered, one barrier per plane) for the x and y neighbours.
+//  - Global traffic is x-contiguous 16-byte vectors: u^n once per point (plus
+//    the halo), u^{n-1} and c streamed with nontemporal loads, u^{n+1} written
+//    with nontemporal stores.  Every load of the next plane is issued one plane
+//    ahead of its use.
+//  - Sources and receivers are fused: a CSR event list over (x, y) columns,
+//    sorted by z, gives each thread the next plane where one of its columns has
+//    an event; only that plane takes the slow path.
+//  - Workgroup ids are remapped so that a contiguous run of tiles lands on one
+//    XCD (workgroups are dealt round-robin to the 8 XCDs), which keeps halo
+//    re-reads inside that XCD's L2.
+//
+// Field layout (padded): element (x, y, z) of the interior sits at
+// off0 + z * pxy + y * px + x; at least R zero ghost cells surround the
+// interior on every face (the zero solution outside the domain, Sec. 1) and
+// rows/planes carry alignment padding so that every tile load is in bounds.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fd_types.h"
+
+#pragma clang fp contract(off)
+
+namespace fdw {
+
+// ------------------------------------------------------------------ weights
+
+constexpr double factorial(int n)
+{
+    double f = 1.0;
+    for (int i = 2; i <= n; ++i) f *= (double)i;
+    return f;
+}
+
+// Exact central weight of the radius-r second-derivative stencil:
+// w_l = 2 (-1)^{l+1} (r!)^2 / (l^2 (r-l)! (r+l)!).  For r <= 8 the numerator and
+// denominator are integers below 2^53, so the single division is correctly rounded.
+constexpr double stencil_weight(int r, int l)
+{
+    double num = 2.0 * factorial(r) * factorial(r);
+    double den = (double)l * (double)l * factorial(r - l) * factorial(r + l);
+    double w = num / den;
+    return (l % 2 == 1) ? w : -w;
+}
+
+template <int R>
+struct StencilWeights {
+    double w[R + 1];
+    constexpr StencilWeights() : w()
+    {
+        double s = 0.0;
+        for (int l = 1; l <= R; ++l) {
+            w[l] = stencil_weight(R, l);
+            s += w[l];
+        }
+        w[0] = -2.0 * s;
+    }
+};
+
+// ------------------------------------------------------------------ 16-byte vectors
+
+template <typename T>
+struct V16;
+template <>
+struct V16<float> {
+    typedef float t __attribute__((ext_vector_type(4)));
+    static constexpr int N = 4;
+};
+template <>
+struct V16<double> {
+    typedef double t __attribute__((ext_vector_type(2)));
+    static constexpr int N = 2;
+};
+
+template <typename T>
+__device__ __forceinline__ void vld(T (&d)[V16<T>::N], const T *p)
+{
+    typename V16<T>::t v = *reinterpret_cast<const typename V16<T>::t *>(p);
+#pragma unroll
+    for (int i = 0; i < V16<T>::N; ++i) d[i] = v[i];
+}
+
+template <typename T>
+__device__ __forceinline__ void vld_nt(T (&d)[V16<T>::N], const T *p)
+{
+    typename V16<T>::t v = __builtin_nontemporal_load(reinterpret_cast<const typename V16<T>::t *>(p));
+#pragma unroll
+    for (int i = 0; i < V16<T>::N; ++i) d[i] = v[i];
+}
+
+template <typename T>
+__device__ __forceinline__ void vst(T *p, const T (&s)[V16<T>::N])
+{
+    typename V16<T>::t v;
+#pragma unroll
+    for (int i = 0; i < V16<T>::N; ++i) v[i] = s[i];
+    *reinterpret_cast<typename V16<T>::t *>(p) = v;
+}
+
+template <typename T>
+__device__ __forceinline__ void vst_nt(T *p, const T (&s)[V16<T>::N])
+{
+    typename V16<T>::t v;
+#pragma unroll
+    for (int i = 0; i < V16<T>::N; ++i) v[i] = s[i];
+    __builtin_nontemporal_store(v, reinterpret_cast<typename V16<T>::t *>(p));
+}
+
+template <typename T, int N>
+__device__ __forceinline__ void vzero(T (&d)[N])
+{
+#pragma unroll
+    for (int i = 0; i < N; ++i) d[i] = T(0);
+}
+
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// Workgroups are dealt round-robin to the 8 XCDs; give each XCD a contiguous run of
+// logical tile ids so that neighbouring tiles share an L2.  Bijective for any G.
+__device__ __forceinline__ int xcd_remap(int b, int G)
+{
+    constexpr int NX = 8;
+    const int q = G / NX, rem = G % NX;
+    const int xcd = b % NX, idx = b / NX;
+    return (xcd < rem) ? xcd * (q + 1) + idx : rem * (q + 1) + (xcd - rem) * q + idx;
+}
+
+__device__ __forceinline__ int lower_bound_z(const Event *ev, int lo, int hi, int z)
+{
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (ev[mid].z < z)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// ------------------------------------------------------------------ tile configuration
+
+template <typename T, int R_, int NDIM_, int TXN_, int TYN_, int EY_>
+struct TileCfg {
+    typedef T type;
+    static constexpr int R = R_;
+    static constexpr int NDIM = NDIM_;
+    static constexpr int TXN = TXN_;                       // threads along x
+    static constexpr int TYN = (NDIM_ == 3) ? TYN_ : 1;    // threads along y
+    static constexpr int EY = (NDIM_ == 3) ? EY_ : 1;      // rows per thread
+    static constexpr int VEC = V16<T>::N;                  // x points per thread
+    static constexpr int NT = TXN * TYN;
+    static constexpr int BX = TXN * VEC;
+    static constexpr int BY = TYN * EY;
+    static constexpr int LPAD = (R + VEC - 1) / VEC * VEC; // x halo rounded to vectors
+    static constexpr int LW = BX + 2 * LPAD;               // LDS row length
+    static constexpr int HY = (NDIM == 3) ? R : 0;         // y halo rows
+    static constexpr int LH = BY + 2 * HY;
+    static constexpr int LDS = LW * LH;                    // elements per LDS plane
+    static constexpr int NXV = 2 * LPAD / VEC + 1;         // vectors read per row for x neighbours
+    static constexpr int NHY = 2 * HY * TXN;               // y-halo vectors per plane
+    static constexpr int NHS = LPAD / VEC;                 // x-halo vectors per side per row
+    static constexpr int NHX = 2 * BY * NHS;
+    static constexpr int NH = NHY + NHX;
+    static constexpr int HPT = (NH + NT - 1) / NT;         // halo vectors per thread
+    static constexpr int YR = EY + 2 * HY;                 // rows a thread touches along y
+    static_assert(256 % BX == 0 && 64 % BY == 0, "tile must divide the layout alignment");
+};
+
+// Per-thread geometry of one tile, shared by the forward and adjoint kernels.
+template <class C>
+struct TileGeom {
+    int lx, ly, gx, gy, x0, y0, z0, z1;
+    int64_t col;             // element offset of (gx, gy, 0)
+    bool rin[C::EY];         // row e of this thread lies inside the grid (computed and stored)
+    bool lin[C::EY];         // row e lies inside the grid or its R-wide ghost ring (loaded)
+    int64_t hoff[C::HPT];    // halo vector k: element offset at z = 0
+    int hl[C::HPT];          // halo vector k: LDS offset
+    bool hval[C::HPT];
+
+    __device__ __forceinline__ void init(const ShotDesc &s, int tx, int ty, int cz)
+    {
+        const int tid = threadIdx.x;
+        lx = (tid % C::TXN) * C::VEC;
+        ly = (tid / C::TXN) * C::EY;
+        x0 = tx * C::BX;
+        y0 = ty * C::BY;
+        gx = x0 + lx;
+        gy = y0 + ly;
+        z0 = cz * s.zch;
+        z1 = min(z0 + s.zch, s.nz);
+        col = s.off0 + (int64_t)gy * s.px + gx;
+#pragma unroll
+        for (int e = 0; e < C::EY; ++e) {
+            rin[e] = (gx < s.nx) && (gy + e < s.ny);
+            lin[e] = (gx < s.nx + C::R) && (gy + e < s.ny + C::HY);
+        }
+#pragma unroll
+        for (int k = 0; k < C::HPT; ++k) {
+            const int hv = tid + k * C::NT;
+            hval[k] = hv < C::NH;
+            int ry = 0, cx = 0;
+            if (hv < C::NHY) {
+                const int ri = hv / C::TXN;
+                cx = (hv % C::TXN) * C::VEC;
+                ry = (ri < C::HY) ? ri - C::HY : C::BY + (ri - C::HY);
+            } else if (hv < C::NH) {
+                const int hx = hv - C::NHY;
+                ry = hx / (2 * C::NHS);
+                const int si = hx % (2 * C::NHS);
+                cx = (si < C::NHS) ? -C::LPAD + si * C::VEC : C::BX + (si - C::NHS) * C::VEC;
+            }
+            hoff[k] = s.off0 + (int64_t)(y0 + ry) * s.px + (x0 + cx);
+            hl[k] = (ry + C::HY) * C::LW + (cx + C::LPAD);
+        }
+    }
+};
+
+// Next plane >= z at which one of this thread's columns has an event (INT_MAX if none).
+template <class C>
+__device__ __forceinline__ int next_event(const ShotDesc &s, const TileGeom<C> &g, int z)
+{
+    int nxt = 0x7fffffff;
+    if (!s.ev_ptr) return nxt;
+#pragma unroll
+    for (int e = 0; e < C::EY; ++e) {
+#pragma unroll
+        for (int v = 0; v < C::VEC; ++v) {
+            if (g.rin[e] && g.gx + v < s.nx) {
+                const int cidx = (g.gy + e) * s.nx + g.gx + v;
+                const int lo = s.ev_ptr[cidx], hi = s.ev_ptr[cidx + 1];
+                if (lo < hi) {
+                    const int p = lower_bound_z(s.ev, lo, hi, z);
+                    if (p < hi) nxt = min(nxt, s.ev[p].z);
+                }
+            }
+        }
+    }
+    return nxt;
+}
+
+// ------------------------------------------------------------------ forward step
+
+template <class C>
+__device__ __forceinline__ void fwd_tile(const ShotDesc &s, const typename C::type *__restrict__ cur,
+                                         const typename C::type *prev, typename C::type *out,
+                                         int64_t step, bool record, int tx, int ty, int cz,
+                                         typename C::type *lds)
+{
+    typedef typename C::type T;
+    constexpr int R = C::R, VEC = C::VEC, EY = C::EY, HPT = C::HPT, HY = C::HY;
+    constexpr StencilWeights<R> W{};
+    const T *__restrict__ cc = static_cast<const T *>(s.c);
+    const int64_t px = s.px, pxy = s.pxy;
+
+    TileGeom<C> g;
+    g.init(s, tx, ty, cz);
+    if (g.z0 >= g.z1) return;
+
+    // register queue: q[k] holds u^n at plane z - R + k
+    T q[2 * R + 1][EY][VEC];
+#pragma unroll
+    for (int k = 0; k < 2 * R; ++k)
+#pragma unroll
+        for (int e = 0; e < EY; ++e) {
+            if (g.lin[e])
+                vld(q[k][e], cur + g.col + e * px + (int64_t)(g.z0 - R + k) * pxy);
+            else
+                vzero(q[k][e]);
+        }
+    // prefetch registers for the plane about to be processed
+    T nu[EY][VEC], npv[EY][VEC], ncc[EY][VEC], nh[HPT][VEC];
+    {
+        const int64_t zo = (int64_t)g.z0 * pxy;
+#pragma unroll
+        for (int e = 0; e < EY; ++e) {
+            if (g.lin[e])
+                vld(nu[e], cur + g.col + e * px + zo + R * pxy);
+            else
+                vzero(nu[e]);
+            if (g.rin[e]) {
+                vld_nt(npv[e], prev + g.col + e * px + zo);
+                vld_nt(ncc[e], cc + g.col + e * px + zo);
+            } else {
+                vzero(npv[e]);
+                vzero(ncc[e]);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < HPT; ++k) {
+            if (g.hval[k])
+                vld(nh[k], cur + g.hoff[k] + zo);
+            else
+                vzero(nh[k]);
+        }
+    }
+    int nev = next_event<C>(s, g, g.z0);
+
+    int buf = 0;
+    for (int z = g.z0; z < g.z1; ++z) {
+        T pv[EY][VEC], cv[EY][VEC], hv[HPT][VEC];
+#pragma unroll
+        for (int e = 0; e < EY; ++e)
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) {
+                q[2 * R][e][v] = nu[e][v];
+                pv[e][v] = npv[e][v];
+                cv[e][v] = ncc[e][v];
+            }
+#pragma unroll
+        for (int k = 0; k < HPT; ++k)
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) hv[k][v] = nh[k][v];
+
+        if (z + 1 < g.z1) {
+            const int64_t zo = (int64_t)(z + 1) * pxy;
+#pragma unroll
+            for (int e = 0; e < EY; ++e) {
+                if (g.lin[e]) vld(nu[e], cur + g.col + e * px + zo + R * pxy);
+                if (g.rin[e]) {
+                    vld_nt(npv[e], prev + g.col + e * px + zo);
+                    vld_nt(ncc[e], cc + g.col + e * px + zo);
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < HPT; ++k)
+                if (g.hval[k]) vld(nh[k], cur + g.hoff[k] + zo);
+        }
+
+        // stage plane z (interior from the queue, halo from the prefetch) in LDS
+        T *L = lds + buf * C::LDS;
+#pragma unroll
+        for (int e = 0; e < EY; ++e) vst(L + (g.ly + e + HY) * C::LW + C::LPAD + g.lx, q[R][e]);
+#pragma unroll
+        for (int k = 0; k < HPT; ++k)
+            if (g.hval[k]) vst(L + g.hl[k], hv[k]);
+        __syncthreads();
+
+        // y neighbour rows: yr[k] is row ly - HY + k at this thread's x vector
+        T yr[C::YR][VEC];
+#pragma unroll
+        for (int k = 0; k < C::YR; ++k) {
+            if (k >= HY && k < HY + EY) {
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) yr[k][v] = q[R][k - HY][v];
+            } else {
+                vld(yr[k], L + (g.ly + k) * C::LW + C::LPAD + g.lx);
+            }
+        }
+
+        T un[EY][VEC];
+#pragma unroll
+        for (int e = 0; e < EY; ++e) {
+            T xs[C::NXV * VEC];
+#pragma unroll
+            for (int j = 0; j < C::NXV; ++j) {
+                T tmp[VEC];
+                vld(tmp, L + (g.ly + e + HY) * C::LW + g.lx + j * VEC);
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) xs[j * VEC + v] = tmp[v];
+            }
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) {
+                const T u0 = q[R][e][v];
+                T acc = T(0);
+#pragma unroll
+                for (int l = 1; l <= R; ++l)
+                    acc = fma_t(T(W.w[l]), (xs[C::LPAD + v + l] - u0) + (xs[C::LPAD + v - l] - u0), acc);
+                if (C::NDIM == 3) {
+#pragma unroll
+                    for (int l = 1; l <= R; ++l)
+                        acc = fma_t(T(W.w[l]), (yr[HY + e + l][v] - u0) + (yr[HY + e - l][v] - u0), acc);
+                }
+#pragma unroll
+                for (int l = 1; l <= R; ++l)
+                    acc = fma_t(T(W.w[l]), (q[R + l][e][v] - u0) + (q[R - l][e][v] - u0), acc);
+                un[e][v] = fma_t(cv[e][v], acc, T(2) * u0 - pv[e][v]);
+            }
+        }
+
+        // fused sources (added before the store) and receivers (recorded after them)
+        if (z == nev) {
+            int nxt = 0x7fffffff;
+#pragma unroll
+            for (int e = 0; e < EY; ++e) {
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) {
+                    if (g.rin[e] && g.gx + v < s.nx) {
+                        const int cidx = (g.gy + e) * s.nx + g.gx + v;
+                        const int lo = s.ev_ptr[cidx], hi = s.ev_ptr[cidx + 1];
+                        if (lo < hi) {
+                            int p = lower_bound_z(s.ev, lo, hi, z);
+                            for (; p < hi && s.ev[p].z == z; ++p) {
+                                const int code = s.ev[p].code;
+                                if (code < 0) {
+                                    const SourceInfo si = s.src[~code];
+                                    if (step < si.nsamp)
+                                        un[e][v] += T(si.scale) * static_cast<const T *>(si.wav)[step];
+                                } else if (record) {
+                                    const int64_t row = step - s.rec_base;
+                                    if (row >= 0 && row < s.rec_cap)
+                                        static_cast<T *>(s.traces)[row * s.nrec + code] = un[e][v];
+                                }
+                            }
+                            if (p < hi) nxt = min(nxt, s.ev[p].z);
+                        }
+                    }
+                }
+            }
+            nev = nxt;
+        }
+
+#pragma unroll
+        for (int e = 0; e < EY; ++e) {
+            if (g.rin[e]) {
+                T *p = out + g.col + e * px + (int64_t)z * pxy;
+                if (g.gx + VEC <= s.nx) {
+                    vst_nt(p, un[e]);
+                } else {
+#pragma unroll
+                    for (int v = 0; v < VEC; ++v)
+                        if (g.gx + v < s.nx) p[v] = un[e][v];
+                }
+            }
+        }
+
+#pragma unroll
+        for (int k = 0; k < 2 * R; ++k)
+#pragma unroll
+            for (int e = 0; e < EY; ++e)
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) q[k][e][v] = q[k + 1][e][v];
+        buf ^= 1;
+    }
+}
+
+template <class C>
+__global__ __launch_bounds__(C::NT) void fwd_kernel(LaunchArgs a)
+{
+    typedef typename C::type T;
+    __shared__ __attribute__((aligned(16))) T lds[2 * C::LDS];
+    int wg = blockIdx.x;
+    if (a.xcd_remap) wg = xcd_remap(wg, (int)gridDim.x);
+    int shot = 0, local = wg;
+    if (a.nshots > 1) {
+        int lo = 0, hi = a.nshots;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (a.wg_prefix[mid] <= wg)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        shot = lo;
+        local = wg - a.wg_prefix[lo];
+    }
+    ShotDesc *sp = a.shots + shot;
+    int64_t step;
+    if (a.step >= 0) {
+        step = a.step;
+    } else {
+        step = sp->ctr[a.slot];
+        const bool active = step < sp->target;
+        if (local == 0 && threadIdx.x == 0) sp->ctr[a.slot ^ 1] = active ? step + 1 : step;
+        if (!active) return;
+    }
+    const ShotDesc &s = *sp;
+    const T *cur;
+    const T *prev;
+    T *out;
+    if (a.cur) {
+        cur = static_cast<const T *>(a.cur);
+        prev = static_cast<const T *>(a.prev);
+        out = static_cast<T *>(a.out);
+    } else {
+        cur = static_cast<const T *>(s.buf[step & 1]);
+        prev = static_cast<const T *>(s.buf[(step + 1) & 1]);
+        out = static_cast<T *>(s.buf[(step + 1) & 1]);
+    }
+    const int tx = local % s.tiles_x;
+    const int t2 = local / s.tiles_x;
+    const int ty = t2 % s.tiles_y;
+    const int cz = t2 / s.tiles_y;
+    if (cz >= s.chunks_z) return;
+    fwd_tile<C>(s, cur, prev, out, step, a.record != 0, tx, ty, cz, lds);
+}
+
+// ------------------------------------------------------------------ adjoint step
+
+// One step of the discrete adjoint in the variable mu = c * lambda, fused with the
+// imaging condition:
+//     mu^k = 2 mu^{k+1} - mu^{k+2} + c Lh mu^{k+1} + resid_amp c_j resid[k-1][j] e_j
+//     g   += mu^k * Lh u^{k-1}
+// Two register queues (mu^{k+1}, u^{k-1}) march in z together; both planes are
+// staged in LDS.
+template <class C>
+__device__ __forceinline__ void adj_tile(const ShotDesc &s, const typename C::type *__restrict__ mcur,
+                                         typename C::type *mout, const typename C::type *__restrict__ ucur,
+                                         typename C::type *grad, const typename C::type *__restrict__ resid,
+                                         int64_t k, typename C::type ramp, int tx, int ty, int cz,
+                                         typename C::type *lds)
+{
+    typedef typename C::type T;
+    constexpr int R = C::R, VEC = C::VEC, EY = C::EY, HPT = C::HPT, HY = C::HY;
+    constexpr StencilWeights<R> W{};
+    const T *__restrict__ cc = static_cast<const T *>(s.c);
+    const int64_t px = s.px, pxy = s.pxy;
+
+    TileGeom<C> g;
+    g.init(s, tx, ty, cz);
+    if (g.z0 >= g.z1) return;
+
+    T qm[2 * R + 1][EY][VEC], qu[2 * R + 1][EY][VEC];
+#pragma unroll
+    for (int j = 0; j < 2 * R; ++j)
+#pragma unroll
+        for (int e = 0; e < EY; ++e) {
+            if (g.lin[e]) {
+                vld(qm[j][e], mcur + g.col + e * px + (int64_t)(g.z0 - R + j) * pxy);
+                vld(qu[j][e], ucur + g.col + e * px + (int64_t)(g.z0 - R + j) * pxy);
+            } else {
+                vzero(qm[j][e]);
+                vzero(qu[j][e]);
+            }
+        }
+    T nm[EY][VEC], nuu[EY][VEC], npv[EY][VEC], ncc[EY][VEC], ngr[EY][VEC], nhm[HPT][VEC], nhu[HPT][VEC];
+    {
+        const int64_t zo = (int64_t)g.z0 * pxy;
+#pragma unroll
+        for (int e = 0; e < EY; ++e) {
+            if (g.lin[e]) {
+                vld(nm[e], mcur + g.col + e * px + zo + R * pxy);
+                vld(nuu[e], ucur + g.col + e * px + zo + R * pxy);
+            } else {
+                vzero(nm[e]);
+                vzero(nuu[e]);
+            }
+            if (g.rin[e]) {
+                vld_nt(npv[e], mout + g.col + e * px + zo);
+                vld_nt(ncc[e], cc + g.col + e * px + zo);
+                vld_nt(ngr[e], grad + g.col + e * px + zo);
+            } else {
+                vzero(npv[e]);
+                vzero(ncc[e]);
+                vzero(ngr[e]);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < HPT; ++j) {
+            if (g.hval[j]) {
+                vld(nhm[j], mcur + g.hoff[j] + zo);
+                vld(nhu[j], ucur + g.hoff[j] + zo);
+            } else {
+                vzero(nhm[j]);
+                vzero(nhu[j]);
+            }
+        }
+    }
+    int nev = next_event<C>(s, g, g.z0);
+
+    int buf = 0;
+    for (int z = g.z0; z < g.z1; ++z) {
+        T pv[EY][VEC], cv[EY][VEC], gv[EY][VEC], hm[HPT][VEC], hu[HPT][VEC];
+#pragma unroll
+        for (int e = 0; e < EY; ++e)
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) {
+                qm[2 * R][e][v] = nm[e][v];
+                qu[2 * R][e][v] = nuu[e][v];
+                pv[e][v] = npv[e][v];
+                cv[e][v] = ncc[e][v];
+                gv[e][v] = ngr[e][v];
+            }
+#pragma unroll
+        for (int j = 0; j < HPT; ++j)
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) {
+                hm[j][v] = nhm[j][v];
+                hu[j][v] = nhu[j][v];
+            }
+        if (z + 1 < g.z1) {
+            const int64_t zo = (int64_t)(z + 1) * pxy;
+#pragma unroll
+            for (int e = 0; e < EY; ++e) {
+                if (g.lin[e]) {
+                    vld(nm[e], mcur + g.col + e * px + zo + R * pxy);
+                    vld(nuu[e], ucur + g.col + e * px + zo + R * pxy);
+                }
+                if (g.rin[e]) {
+                    vld_nt(npv[e], mout + g.col + e * px + zo);
+                    vld_nt(ncc[e], cc + g.col + e * px + zo);
+                    vld_nt(ngr[e], grad + g.col + e * px + zo);
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < HPT; ++j)
+                if (g.hval[j]) {
+                    vld(nhm[j], mcur + g.hoff[j] + zo);
+                    vld(nhu[j], ucur + g.hoff[j] + zo);
+                }
+        }
+
+        T *Lm = lds + buf * (2 * C::LDS);
+        T *Lu = Lm + C::LDS;
+#pragma unroll
+        for (int e = 0; e < EY; ++e) {
+            vst(Lm + (g.ly + e + HY) * C::LW + C::LPAD + g.lx, qm[R][e]);
+            vst(Lu + (g.ly + e + HY) * C::LW + C::LPAD + g.lx, qu[R][e]);
+        }
+#pragma unroll
+        for (int j = 0; j < HPT; ++j)
+            if (g.hval[j]) {
+                vst(Lm + g.hl[j], hm[j]);
+                vst(Lu + g.hl[j], hu[j]);
+            }
+        __syncthreads();
+
+        T mnew[EY][VEC], lapu[EY][VEC];
+#pragma unroll
+        for (int pass = 0; pass < 2; ++pass) {
+            const T *Lp = pass == 0 ? Lm : Lu;
+            T yr[C::YR][VEC];
+#pragma unroll
+            for (int j = 0; j < C::YR; ++j) {
+                if (j >= HY && j < HY + EY) {
+#pragma unroll
+                    for (int v = 0; v < VEC; ++v) yr[j][v] = pass == 0 ? qm[R][j - HY][v] : qu[R][j - HY][v];
+                } else {
+                    vld(yr[j], Lp + (g.ly + j) * C::LW + C::LPAD + g.lx);
+                }
+            }
+#pragma unroll
+            for (int e = 0; e < EY; ++e) {
+                T xs[C::NXV * VEC];
+#pragma unroll
+                for (int j = 0; j < C::NXV; ++j) {
+                    T tmp[VEC];
+                    vld(tmp, Lp + (g.ly + e + HY) * C::LW + g.lx + j * VEC);
+#pragma unroll
+                    for (int v = 0; v < VEC; ++v) xs[j * VEC + v] = tmp[v];
+                }
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) {
+                    const T u0 = pass == 0 ? qm[R][e][v] : qu[R][e][v];
+                    T acc = T(0);
+#pragma unroll
+                    for (int l = 1; l <= R; ++l)
+                        acc = fma_t(T(W.w[l]), (xs[C::LPAD + v + l] - u0) + (xs[C::LPAD + v - l] - u0), acc);
+                    if (C::NDIM == 3) {
+#pragma unroll
+                        for (int l = 1; l <= R; ++l)
+                            acc = fma_t(T(W.w[l]), (yr[HY + e + l][v] - u0) + (yr[HY + e - l][v] - u0), acc);
+                    }
+#pragma unroll
+                    for (int l = 1; l <= R; ++l) {
+                        const T zp = pass == 0 ? qm[R + l][e][v] : qu[R + l][e][v];
+                        const T zm = pass == 0 ? qm[R - l][e][v] : qu[R - l][e][v];
+                        acc = fma_t(T(W.w[l]), (zp - u0) + (zm - u0), acc);
+                    }
+                    if (pass == 0)
+                        mnew[e][v] = fma_t(cv[e][v], acc, T(2) * u0 - pv[e][v]);
+                    else
+                        lapu[e][v] = acc;
+                }
+            }
+        }
+
+        // adjoint sources: the residual enters at the receivers, scaled by c there
+        if (z == nev) {
+            int nxt = 0x7fffffff;
+#pragma unroll
+            for (int e = 0; e < EY; ++e) {
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) {
+                    if (g.rin[e] && g.gx + v < s.nx) {
+                        const int cidx = (g.gy + e) * s.nx + g.gx + v;
+                        const int lo = s.ev_ptr[cidx], hi = s.ev_ptr[cidx + 1];
+                        if (lo < hi) {
+                            int p = lower_bound_z(s.ev, lo, hi, z);
+                            for (; p < hi && s.ev[p].z == z; ++p) {
+                                const int code = s.ev[p].code;
+                                if (code >= 0)
+                                    mnew[e][v] = fma_t(ramp * cv[e][v], resid[(k - 1) * s.nrec + code], mnew[e][v]);
+                            }
+                            if (p < hi) nxt = min(nxt, s.ev[p].z);
+                        }
+                    }
+                }
+            }
+            nev = nxt;
+        }
+
+#pragma unroll
+        for (int e = 0; e < EY; ++e) {
+            T gn[VEC];
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) gn[v] = fma_t(mnew[e][v], lapu[e][v], gv[e][v]);
+            if (g.rin[e]) {
+                T *pm = mout + g.col + e * px + (int64_t)z * pxy;
+                T *pg = grad + g.col + e * px + (int64_t)z * pxy;
+                if (g.gx + VEC <= s.nx) {
+                    vst_nt(pm, mnew[e]);
+                    vst_nt(pg, gn);
+                } else {
+#pragma unroll
+                    for (int v = 0; v < VEC; ++v)
+                        if (g.gx + v < s.nx) {
+                            pm[v] = mnew[e][v];
+                            pg[v] = gn[v];
+                        }
+                }
+            }
+        }
+
+#pragma unroll
+        for (int j = 0; j < 2 * R; ++j)
+#pragma unroll
+            for (int e = 0; e < EY; ++e)
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) {
+                    qm[j][e][v] = qm[j + 1][e][v];
+                    qu[j][e][v] = qu[j + 1][e][v];
+                }
+        buf ^= 1;
+    }
+}
+
+template <class C>
+__global__ __launch_bounds__(C::NT) void adj_kernel(AdjArgs a)
+{
+    typedef typename C::type T;
+    __shared__ __attribute__((aligned(16))) T lds[4 * C::LDS];
+    int wg = blockIdx.x;
+    if (a.xcd_remap) wg = xcd_remap(wg, (int)gridDim.x);
+    const ShotDesc &s = *a.shot;
+    const int tx = wg % s.tiles_x;
+    const int t2 = wg / s.tiles_x;
+    const int ty = t2 % s.tiles_y;
+    const int cz = t2 / s.tiles_y;
+    if (cz >= s.chunks_z) return;
+    adj_tile<C>(s, static_cast<const T *>(a.mu_cur), static_cast<T *>(a.mu_out),
+                static_cast<const T *>(a.u_km1), static_cast<T *>(a.grad),
+                static_cast<const T *>(a.resid), a.k, T(a.resid_amp), tx, ty, cz, lds);
+}
+
+// ------------------------------------------------------------------ registry
+
+struct FwdEntry {
+    const char *name;
+    int bx, by, nt;
+    void (*launch)(const LaunchArgs &, int nwg, hipStream_t);
+};
+
+struct AdjEntry {
+    const char *name;
+    int bx, by, nt;
+    void (*launch)(const AdjArgs &, int nwg, hipStream_t);
+};
+
+template <class C>
+void launch_fwd(const LaunchArgs &a, int nwg, hipStream_t st)
+{
+    hipLaunchKernelGGL(fwd_kernel<C>, dim3(nwg), dim3(C::NT), 0, st, a);
+}
+
+template <class C>
+void launch_adj(const AdjArgs &a, int nwg, hipStream_t st)
+{
+    hipLaunchKernelGGL(adj_kernel<C>, dim3(nwg), dim3(C::NT), 0, st, a);
+}
+
+template <class C>
+constexpr FwdEntry fwd_entry(const char *name)
+{
+    return FwdEntry{name, C::BX, C::BY, C::NT, &launch_fwd<C>};
+}
+
+template <class C>
+constexpr AdjEntry adj_entry(const char *name)
+{
+    return AdjEntry{name, C::BX, C::BY, C::NT, &launch_adj<C>};
+}
+
+// Implemented in the per-dtype translation units.
+const FwdEntry *fwd_configs_f32(int r, int ndim, int *count);
+const FwdEntry *fwd_configs_f64(int r, int ndim, int *count);
+const AdjEntry *adj_config_f32(int r, int ndim);
+const AdjEntry *adj_config_f64(int r, int ndim);
+
+}  // namespace fdw

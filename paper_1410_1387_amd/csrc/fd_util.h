@@ -1,0 +1,28 @@
+// fd_util.h -- launchers of the element-wise kernels in fd_util.hip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fdw {
+
+// Interior extent and padded addressing of one field (kernel axes: 2-D grids use
+// nx = grid nx, ny = 1, nz = grid ny).
+struct Geom {
+    int64_t nx, ny, nz;
+    int64_t px, pxy, off0;
+};
+
+constexpr int kPrepBlocks = 1024;  // partial min/max slots the prep kernel writes
+
+hipError_t launch_prep(int dtype, const Geom &g, const void *v, void *c, double k, double *partial,
+                       double *minmax, hipStream_t st);
+hipError_t launch_pack(int dtype, const Geom &g, const void *padded, void *dense, hipStream_t st);
+hipError_t launch_unpack(int dtype, const Geom &g, const void *dense, void *padded, hipStream_t st);
+hipError_t launch_halo_periodic(int dtype, const Geom &g, int hx, int hy, int hz, void *u, hipStream_t st);
+hipError_t launch_ricker(int dtype, void *out, int64_t nsamp, double dt, double f0, double t0, hipStream_t st);
+hipError_t launch_grad_finish(int dtype, const Geom &g, const void *gpad, const void *v, void *out, double scale,
+                              hipStream_t st);
+hipError_t launch_copy_probe(void *dst, const void *src, size_t bytes, hipStream_t st);
+
+}  // namespace fdw

@@ -1,0 +1,239 @@
+// fd_util.hip -- element-wise device kernels around the stencil: model preparation
+// (v -> c = (v dt / h)^2 in the padded layout, with min/max of v), dense <-> padded
+// copies, the periodic ghost fill, Ricker samples, the gradient finish and the
+// bandwidth probe.  All are HBM-bound streaming kernels with grid-stride loops.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "fd_util.h"
+
+namespace fdw {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+inline int blocks_for(int64_t n, int cap = 8192)
+{
+    int64_t b = (n + kThreads - 1) / kThreads;
+    if (b < 1) b = 1;
+    if (b > cap) b = cap;
+    return (int)b;
+}
+
+__device__ __forceinline__ int64_t padded_offset(const Geom &g, int64_t i)
+{
+    const int64_t x = i % g.nx;
+    const int64_t t = i / g.nx;
+    const int64_t y = t % g.ny;
+    const int64_t z = t / g.ny;
+    return g.off0 + z * g.pxy + y * g.px + x;
+}
+
+template <typename T>
+__global__ void prep_kernel(Geom g, const T *__restrict__ v, T *__restrict__ c, double k,
+                            double *__restrict__ partial)
+{
+    __shared__ double smin[kThreads], smax[kThreads];
+    const int64_t n = (int64_t)g.nx * g.ny * g.nz;
+    double lo = INFINITY, hi = -INFINITY;
+    bool bad = false;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double vi = (double)v[i];
+        if (!(vi > 0.0) || !isfinite(vi)) bad = true;
+        lo = fmin(lo, vi);
+        hi = fmax(hi, vi);
+        c[padded_offset(g, i)] = (T)(k * vi * vi);
+    }
+    if (bad) lo = -1.0;  // reported as an invalid velocity
+    smin[threadIdx.x] = lo;
+    smax[threadIdx.x] = hi;
+    __syncthreads();
+    for (int s = kThreads / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + s]);
+            smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + s]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partial[2 * blockIdx.x] = smin[0];
+        partial[2 * blockIdx.x + 1] = smax[0];
+    }
+}
+
+__global__ void minmax_final(const double *__restrict__ partial, int nb, double *__restrict__ out)
+{
+    __shared__ double smin[kThreads], smax[kThreads];
+    double lo = INFINITY, hi = -INFINITY;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+        lo = fmin(lo, partial[2 * i]);
+        hi = fmax(hi, partial[2 * i + 1]);
+    }
+    smin[threadIdx.x] = lo;
+    smax[threadIdx.x] = hi;
+    __syncthreads();
+    for (int s = kThreads / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + s]);
+            smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + s]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = smin[0];
+        out[1] = smax[0];
+    }
+}
+
+template <typename T>
+__global__ void pack_kernel(Geom g, const T *__restrict__ padded, T *__restrict__ dense)
+{
+    const int64_t n = (int64_t)g.nx * g.ny * g.nz;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        dense[i] = padded[padded_offset(g, i)];
+}
+
+template <typename T>
+__global__ void unpack_kernel(Geom g, const T *__restrict__ dense, T *__restrict__ padded)
+{
+    const int64_t n = (int64_t)g.nx * g.ny * g.nz;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        padded[padded_offset(g, i)] = dense[i];
+}
+
+// Periodic ghost fill: every cell of the box [-hx, nx+hx) x [-hy, ny+hy) x [-hz, nz+hz)
+// that lies outside the interior takes the value of its wrapped interior image.
+template <typename T>
+__global__ void halo_periodic_kernel(Geom g, int hx, int hy, int hz, T *__restrict__ u)
+{
+    const int64_t ex = g.nx + 2 * hx, ey = g.ny + 2 * hy, ez = g.nz + 2 * hz;
+    const int64_t n = ex * ey * ez;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t x = i % ex - hx;
+        const int64_t t = i / ex;
+        const int64_t y = t % ey - hy;
+        const int64_t z = t / ey - hz;
+        const bool inside = x >= 0 && x < g.nx && y >= 0 && y < g.ny && z >= 0 && z < g.nz;
+        if (inside) continue;
+        const int64_t wx = (x % g.nx + g.nx) % g.nx;
+        const int64_t wy = (y % g.ny + g.ny) % g.ny;
+        const int64_t wz = (z % g.nz + g.nz) % g.nz;
+        u[g.off0 + z * g.pxy + y * g.px + x] = u[g.off0 + wz * g.pxy + wy * g.px + wx];
+    }
+}
+
+template <typename T>
+__global__ void ricker_kernel(T *__restrict__ out, int64_t nsamp, double dt, double f0, double t0)
+{
+    const double pf = 3.14159265358979323846 * f0;
+    for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < nsamp; n += (int64_t)gridDim.x * blockDim.x) {
+        const double tau = (double)n * dt - t0;
+        const double a = pf * pf * tau * tau;
+        out[n] = (T)((1.0 - 2.0 * a) * exp(-a));
+    }
+}
+
+template <typename T>
+__global__ void grad_finish_kernel(Geom g, const T *__restrict__ gpad, const T *__restrict__ v,
+                                   T *__restrict__ out, double scale)
+{
+    const int64_t n = (int64_t)g.nx * g.ny * g.nz;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = (T)(scale * 2.0 * (double)gpad[padded_offset(g, i)] / (double)v[i]);
+}
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+__global__ void copy_probe_kernel(f4 *__restrict__ dst, const f4 *__restrict__ src, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+}  // namespace
+
+template <typename T>
+static hipError_t prep_t(const Geom &g, const void *v, void *c, double k, double *partial, double *minmax,
+                         hipStream_t st)
+{
+    const int64_t n = (int64_t)g.nx * g.ny * g.nz;
+    const int nb = blocks_for(n, kPrepBlocks);
+    hipLaunchKernelGGL(prep_kernel<T>, dim3(nb), dim3(kThreads), 0, st, g, (const T *)v, (T *)c, k, partial);
+    hipLaunchKernelGGL(minmax_final, dim3(1), dim3(kThreads), 0, st, (const double *)partial, nb, minmax);
+    return hipGetLastError();
+}
+
+hipError_t launch_prep(int dtype, const Geom &g, const void *v, void *c, double k, double *partial,
+                       double *minmax, hipStream_t st)
+{
+    return dtype == 0 ? prep_t<float>(g, v, c, k, partial, minmax, st)
+                      : prep_t<double>(g, v, c, k, partial, minmax, st);
+}
+
+hipError_t launch_pack(int dtype, const Geom &g, const void *padded, void *dense, hipStream_t st)
+{
+    const int nb = blocks_for((int64_t)g.nx * g.ny * g.nz);
+    if (dtype == 0)
+        hipLaunchKernelGGL(pack_kernel<float>, dim3(nb), dim3(kThreads), 0, st, g, (const float *)padded, (float *)dense);
+    else
+        hipLaunchKernelGGL(pack_kernel<double>, dim3(nb), dim3(kThreads), 0, st, g, (const double *)padded, (double *)dense);
+    return hipGetLastError();
+}
+
+hipError_t launch_unpack(int dtype, const Geom &g, const void *dense, void *padded, hipStream_t st)
+{
+    const int nb = blocks_for((int64_t)g.nx * g.ny * g.nz);
+    if (dtype == 0)
+        hipLaunchKernelGGL(unpack_kernel<float>, dim3(nb), dim3(kThreads), 0, st, g, (const float *)dense, (float *)padded);
+    else
+        hipLaunchKernelGGL(unpack_kernel<double>, dim3(nb), dim3(kThreads), 0, st, g, (const double *)dense, (double *)padded);
+    return hipGetLastError();
+}
+
+hipError_t launch_halo_periodic(int dtype, const Geom &g, int hx, int hy, int hz, void *u, hipStream_t st)
+{
+    const int64_t n = (int64_t)(g.nx + 2 * hx) * (g.ny + 2 * hy) * (g.nz + 2 * hz);
+    const int nb = blocks_for(n);
+    if (dtype == 0)
+        hipLaunchKernelGGL(halo_periodic_kernel<float>, dim3(nb), dim3(kThreads), 0, st, g, hx, hy, hz, (float *)u);
+    else
+        hipLaunchKernelGGL(halo_periodic_kernel<double>, dim3(nb), dim3(kThreads), 0, st, g, hx, hy, hz, (double *)u);
+    return hipGetLastError();
+}
+
+hipError_t launch_ricker(int dtype, void *out, int64_t nsamp, double dt, double f0, double t0, hipStream_t st)
+{
+    if (nsamp <= 0) return hipSuccess;
+    const int nb = blocks_for(nsamp);
+    if (dtype == 0)
+        hipLaunchKernelGGL(ricker_kernel<float>, dim3(nb), dim3(kThreads), 0, st, (float *)out, nsamp, dt, f0, t0);
+    else
+        hipLaunchKernelGGL(ricker_kernel<double>, dim3(nb), dim3(kThreads), 0, st, (double *)out, nsamp, dt, f0, t0);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad_finish(int dtype, const Geom &g, const void *gpad, const void *v, void *out, double scale,
+                              hipStream_t st)
+{
+    const int nb = blocks_for((int64_t)g.nx * g.ny * g.nz);
+    if (dtype == 0)
+        hipLaunchKernelGGL(grad_finish_kernel<float>, dim3(nb), dim3(kThreads), 0, st, g, (const float *)gpad,
+                           (const float *)v, (float *)out, scale);
+    else
+        hipLaunchKernelGGL(grad_finish_kernel<double>, dim3(nb), dim3(kThreads), 0, st, g, (const double *)gpad,
+                           (const double *)v, (double *)out, scale);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_probe(void *dst, const void *src, size_t bytes, hipStream_t st)
+{
+    const int64_t n = (int64_t)(bytes / 16);
+    if (n == 0) return hipSuccess;
+    const int nb = blocks_for(n, 4 * 256 * 8);
+    hipLaunchKernelGGL(copy_probe_kernel, dim3(nb), dim3(kThreads), 0, st, (f4 *)dst, (const f4 *)src, n);
+    return hipGetLastError();
+}
+
+}  // namespace fdw

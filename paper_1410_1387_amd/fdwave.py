@@ -1,0 +1,290 @@
+"""ctypes binding of libfdwave.so (include/fdwave.h).
+
+Argument marshalling only: each function here has the name of the C entry point it
+wraps, converts Python/torch arguments to plain pointers and sizes, and raises
+``FdError`` on a negative status.  Every step of the computation runs in the HIP
+library; there is no Python or CPU fallback.  If the library is not built the
+first call raises ``RuntimeError``.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfdwave.so")
+
+FD_OK, FD_E_INVAL, FD_E_RANGE, FD_E_UNSTABLE, FD_E_STATE, FD_E_DEVICE, FD_E_NOMEM = 0, -1, -2, -3, -4, -5, -6
+FD_F32, FD_F64 = 0, 1
+FD_BC_ZERO, FD_BC_PERIODIC = 0, 1
+FD_DENSE, FD_PADDED = 0, 1
+
+STATUS_NAMES = {
+    FD_E_INVAL: "FD_E_INVAL", FD_E_RANGE: "FD_E_RANGE", FD_E_UNSTABLE: "FD_E_UNSTABLE",
+    FD_E_STATE: "FD_E_STATE", FD_E_DEVICE: "FD_E_DEVICE", FD_E_NOMEM: "FD_E_NOMEM",
+}
+
+# every symbol include/fdwave.h declares
+EXPORTS = [
+    "fd_weights", "fd_dt_max", "fd_field_bytes", "fd_workspace_bytes", "fd_create", "fd_destroy",
+    "fd_set_stream", "fd_inject", "fd_clear_sources", "fd_record", "fd_ricker", "fd_step", "fd_sync",
+    "fd_get_step", "fd_get_state", "fd_set_state", "fd_step_explicit", "fd_adjoint_segment",
+    "fd_gradient_finish", "fd_batch_workspace_bytes", "fd_batch_create", "fd_batch_destroy",
+    "fd_batch_set", "fd_batch_step", "fd_copy_probe", "fd_kernel_config", "fd_set_tuning",
+    "fd_last_error",
+]
+
+
+class FdError(RuntimeError):
+    def __init__(self, status: int, func: str, msg: str):
+        super().__init__(f"{func}: {STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class FdGrid(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int32), ("n", ctypes.c_int64 * 3)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libfdwave.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() or "
+                               "python paper_1410_1387_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I32, I64, D, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
+        pgrid = ctypes.POINTER(FdGrid)
+        sig = {
+            "fd_weights": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(D)]),
+            "fd_dt_max": (D, [ctypes.c_int, ctypes.c_int, D, D]),
+            "fd_field_bytes": (ctypes.c_int, [pgrid, ctypes.c_int, ctypes.c_int, ctypes.POINTER(SZ)]),
+            "fd_workspace_bytes": (ctypes.c_int, [pgrid, ctypes.c_int, ctypes.c_int, I64, I64, ctypes.POINTER(SZ)]),
+            "fd_create": (ctypes.c_int, [ctypes.POINTER(P), pgrid, ctypes.c_int, D, D, P, ctypes.c_int,
+                                         ctypes.c_int, P, SZ, I64, I64, P]),
+            "fd_destroy": (ctypes.c_int, [P]),
+            "fd_set_stream": (ctypes.c_int, [P, P]),
+            "fd_inject": (ctypes.c_int, [P, P, I64, ctypes.POINTER(I64), D]),
+            "fd_clear_sources": (ctypes.c_int, [P]),
+            "fd_record": (ctypes.c_int, [P, ctypes.POINTER(I32), I64, P, I64]),
+            "fd_ricker": (ctypes.c_int, [P, I64, D, D, D, ctypes.c_int, P]),
+            "fd_step": (ctypes.c_int, [P, I64]),
+            "fd_sync": (ctypes.c_int, [P]),
+            "fd_get_step": (ctypes.c_int, [P, ctypes.POINTER(I64)]),
+            "fd_get_state": (ctypes.c_int, [P, P, P, ctypes.POINTER(I64), ctypes.c_int]),
+            "fd_set_state": (ctypes.c_int, [P, P, P, I64, ctypes.c_int]),
+            "fd_step_explicit": (ctypes.c_int, [P, P, P, P, I64]),
+            "fd_adjoint_segment": (ctypes.c_int, [P, P, P, I64, I64, P, P, P, D, P]),
+            "fd_gradient_finish": (ctypes.c_int, [P, P, P, P, D]),
+            "fd_batch_workspace_bytes": (SZ, [ctypes.c_int]),
+            "fd_batch_create": (ctypes.c_int, [ctypes.POINTER(P), ctypes.c_int, P, SZ, P]),
+            "fd_batch_destroy": (ctypes.c_int, [P]),
+            "fd_batch_set": (ctypes.c_int, [P, ctypes.POINTER(P), ctypes.POINTER(I64), ctypes.c_int]),
+            "fd_batch_step": (ctypes.c_int, [P, I64]),
+            "fd_copy_probe": (ctypes.c_int, [P, P, SZ, P]),
+            "fd_kernel_config": (ctypes.c_char_p, [P]),
+            "fd_set_tuning": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+            "fd_last_error": (ctypes.c_char_p, []),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status: int, func: str):
+    if status != FD_OK:
+        msg = lib().fd_last_error()
+        raise FdError(status, func, msg.decode() if msg else "")
+
+
+def ptr(t) -> Optional[int]:
+    """Raw device (or host) address of a torch tensor, None for None."""
+    if t is None:
+        return None
+    return int(t.data_ptr())
+
+
+def stream_ptr(stream=None) -> Optional[int]:
+    import torch
+
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream) or None
+
+
+def dtype_code(dtype) -> int:
+    import torch
+
+    if dtype in ("f32", torch.float32, FD_F32):
+        return FD_F32
+    if dtype in ("f64", torch.float64, FD_F64):
+        return FD_F64
+    raise ValueError(f"unsupported dtype {dtype}")
+
+
+def make_grid(shape: Sequence[int]) -> FdGrid:
+    """Dense array shape (nz, ny, nx) or (ny, nx) -> fd_grid."""
+    g = FdGrid()
+    g.ndim = len(shape)
+    if g.ndim == 3:
+        g.n[0], g.n[1], g.n[2] = shape[2], shape[1], shape[0]
+    elif g.ndim == 2:
+        g.n[0], g.n[1], g.n[2] = shape[1], shape[0], 1
+    else:
+        raise ValueError("grids are 2-D or 3-D")
+    return g
+
+
+# ------------------------------------------------------------------ thin wrappers, C names
+
+
+def fd_weights(r: int) -> list[float]:
+    w = (ctypes.c_double * (r + 1))()
+    _check(lib().fd_weights(r, w), "fd_weights")
+    return list(w)
+
+
+def fd_dt_max(ndim: int, r: int, h: float, vmax: float) -> float:
+    v = lib().fd_dt_max(ndim, r, h, vmax)
+    if v < 0:
+        raise FdError(FD_E_INVAL, "fd_dt_max", "bad arguments")
+    return v
+
+
+def fd_field_bytes(shape, r: int, dtype) -> int:
+    out = ctypes.c_size_t()
+    _check(lib().fd_field_bytes(ctypes.byref(make_grid(shape)), r, dtype_code(dtype), ctypes.byref(out)),
+           "fd_field_bytes")
+    return out.value
+
+
+def fd_workspace_bytes(shape, r: int, dtype, max_sources: int, max_receivers: int) -> int:
+    out = ctypes.c_size_t()
+    _check(lib().fd_workspace_bytes(ctypes.byref(make_grid(shape)), r, dtype_code(dtype), max_sources,
+                                    max_receivers, ctypes.byref(out)), "fd_workspace_bytes")
+    return out.value
+
+
+def fd_create(shape, r, h, dt, velocity, dtype, bc, workspace, max_sources, max_receivers, stream) -> int:
+    h_ = ctypes.c_void_p()
+    bc_code = FD_BC_PERIODIC if bc in ("periodic", FD_BC_PERIODIC) else FD_BC_ZERO
+    _check(lib().fd_create(ctypes.byref(h_), ctypes.byref(make_grid(shape)), r, float(h), float(dt),
+                           ptr(velocity), dtype_code(dtype), bc_code, ptr(workspace), workspace.numel(),
+                           max_sources, max_receivers, stream), "fd_create")
+    return h_.value
+
+
+def fd_destroy(ctx: int):
+    _check(lib().fd_destroy(ctx), "fd_destroy")
+
+
+def fd_set_stream(ctx: int, stream):
+    _check(lib().fd_set_stream(ctx, stream), "fd_set_stream")
+
+
+def fd_inject(ctx: int, wavelet, pos, amp: float = 1.0):
+    p = (ctypes.c_int64 * 3)(*(list(pos) + [0] * (3 - len(pos))))
+    _check(lib().fd_inject(ctx, ptr(wavelet), wavelet.numel(), p, float(amp)), "fd_inject")
+
+
+def fd_clear_sources(ctx: int):
+    _check(lib().fd_clear_sources(ctx), "fd_clear_sources")
+
+
+def fd_record(ctx: int, positions, traces, cap: int):
+    import numpy as np
+
+    pos = np.zeros((len(positions), 3), dtype=np.int32)
+    if len(positions):
+        pa = np.asarray(positions, dtype=np.int64)
+        pos[:, : pa.shape[1]] = pa
+    _check(lib().fd_record(ctx, pos.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), pos.shape[0],
+                           ptr(traces), int(cap)), "fd_record")
+
+
+def fd_ricker(out, dt: float, f0: float, t0: float, stream):
+    _check(lib().fd_ricker(ptr(out), out.numel(), float(dt), float(f0), float(t0), dtype_code(out.dtype), stream),
+           "fd_ricker")
+
+
+def fd_step(ctx: int, nsteps: int):
+    _check(lib().fd_step(ctx, int(nsteps)), "fd_step")
+
+
+def fd_sync(ctx: int):
+    _check(lib().fd_sync(ctx), "fd_sync")
+
+
+def fd_get_step(ctx: int) -> int:
+    s = ctypes.c_int64()
+    _check(lib().fd_get_step(ctx, ctypes.byref(s)), "fd_get_step")
+    return s.value
+
+
+def fd_get_state(ctx: int, u_cur, u_prev, layout: int = FD_DENSE) -> int:
+    s = ctypes.c_int64()
+    _check(lib().fd_get_state(ctx, ptr(u_cur), ptr(u_prev), ctypes.byref(s), layout), "fd_get_state")
+    return s.value
+
+
+def fd_set_state(ctx: int, u_cur, u_prev, step: int, layout: int = FD_DENSE):
+    _check(lib().fd_set_state(ctx, ptr(u_cur), ptr(u_prev), int(step), layout), "fd_set_state")
+
+
+def fd_step_explicit(ctx: int, cur, prev, out, step: int):
+    _check(lib().fd_step_explicit(ctx, ptr(cur), ptr(prev), ptr(out), int(step)), "fd_step_explicit")
+
+
+def fd_adjoint_segment(ctx: int, ckpt_cur, ckpt_prev, k_lo: int, k_hi: int, ring, mu, resid, resid_amp: float, grad):
+    _check(lib().fd_adjoint_segment(ctx, ptr(ckpt_cur), ptr(ckpt_prev), int(k_lo), int(k_hi), ptr(ring), ptr(mu),
+                                    ptr(resid), float(resid_amp), ptr(grad)), "fd_adjoint_segment")
+
+
+def fd_gradient_finish(ctx: int, grad_padded, velocity, out, scale: float):
+    _check(lib().fd_gradient_finish(ctx, ptr(grad_padded), ptr(velocity), ptr(out), float(scale)),
+           "fd_gradient_finish")
+
+
+def fd_batch_workspace_bytes(max_shots: int) -> int:
+    return int(lib().fd_batch_workspace_bytes(max_shots))
+
+
+def fd_batch_create(max_shots: int, workspace, stream) -> int:
+    h_ = ctypes.c_void_p()
+    _check(lib().fd_batch_create(ctypes.byref(h_), max_shots, ptr(workspace), workspace.numel(), stream),
+           "fd_batch_create")
+    return h_.value
+
+
+def fd_batch_destroy(b: int):
+    _check(lib().fd_batch_destroy(b), "fd_batch_destroy")
+
+
+def fd_batch_set(b: int, ctxs: Sequence[int], targets: Sequence[int]):
+    n = len(ctxs)
+    arr = (ctypes.c_void_p * max(1, n))(*ctxs)
+    tg = (ctypes.c_int64 * max(1, n))(*[int(t) for t in targets])
+    _check(lib().fd_batch_set(b, arr, tg, n), "fd_batch_set")
+
+
+def fd_batch_step(b: int, nsteps: int):
+    _check(lib().fd_batch_step(b, int(nsteps)), "fd_batch_step")
+
+
+def fd_copy_probe(dst, src, nbytes: int, stream):
+    _check(lib().fd_copy_probe(ptr(dst), ptr(src), int(nbytes), stream), "fd_copy_probe")
+
+
+def fd_kernel_config(ctx: int) -> str:
+    return lib().fd_kernel_config(ctx).decode()
+
+
+def fd_set_tuning(dtype, r: int, ndim: int, config: int, zchunk: int = 0):
+    _check(lib().fd_set_tuning(dtype_code(dtype), r, ndim, config, zchunk), "fd_set_tuning")

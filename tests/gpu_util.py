@@ -1,0 +1,66 @@
+"""Helpers for the GPU parity tests: run one shot through the C ABI from numpy inputs
+and return float64 numpy results.  Holds none of the method's arithmetic."""
+
+from __future__ import annotations
+
+import numpy as np
+
+
+def rel_l2(a, b) -> float:
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    nb = np.linalg.norm(b.ravel())
+    return float(np.linalg.norm((a - b).ravel()) / (nb if nb > 0 else 1.0))
+
+
+def say(msg: str):
+    print(f"[gpu] {msg}", flush=True)
+
+
+def run_gpu(v, r, h, dt, T, dtype="f32", sources=(), receivers=None, bc="zero", u0=None, um1=None,
+            tuning=None, ricker=None, label=""):
+    """Forward T steps on the GPU.
+
+    sources   [(pos, samples ndarray)] -- samples are an input shared with the oracle
+    ricker    optional (pos, f0, t0): a Ricker source whose samples the GPU computes itself
+    tuning    optional (config, zchunk) for fd_set_tuning before the context is created
+    Returns dict(u, u_prev, traces, step, config).
+    """
+    import torch
+
+    from paper_1410_1387_amd import Propagator
+    from paper_1410_1387_amd import fdwave as F
+
+    tdt = torch.float32 if dtype == "f32" else torch.float64
+    v = np.asarray(v)
+    ndim = v.ndim
+    say(f"{label} shape={v.shape} r={r} T={T} dtype={dtype} bc={bc} tuning={tuning}")
+    if tuning is not None:
+        F.fd_set_tuning(dtype, r, ndim, tuning[0], tuning[1])
+    try:
+        nrec = 0 if receivers is None else len(receivers)
+        p = Propagator(torch.tensor(v, dtype=tdt, device="cuda"), r, h, dt, dtype=dtype, bc=bc,
+                       max_sources=max(1, len(sources) + (1 if ricker else 0)), max_receivers=nrec)
+    finally:
+        if tuning is not None:
+            F.fd_set_tuning(dtype, r, ndim, 0, 0)
+    for pos, wav in sources:
+        p.inject(torch.tensor(np.asarray(wav), dtype=tdt, device="cuda"), pos)
+    if ricker is not None:
+        pos, f0, t0 = ricker
+        p.inject(p.ricker(T, f0, t0), pos)
+    tr = p.record(receivers, T) if nrec else None
+    if u0 is not None:
+        p.set_state(torch.tensor(u0, dtype=tdt, device="cuda"), torch.tensor(um1, dtype=tdt, device="cuda"), 0)
+    p.step(T)
+    u, up, n = p.state()
+    p.sync()
+    out = {
+        "u": u.double().cpu().numpy(),
+        "u_prev": up.double().cpu().numpy(),
+        "traces": None if tr is None else tr.double().cpu().numpy(),
+        "step": n,
+        "config": p.kernel_config,
+    }
+    p.close()
+    return out

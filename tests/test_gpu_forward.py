@@ -1,0 +1,333 @@
+"""GPU parity of the forward stencil kernel against the FP64 oracle (needs an MI355X).
+
+Bars: FP32 relative L2 <= 1e-4 and FP64 relative L2 <= 1e-11 against the oracle, on
+the final wavefield and on the receiver traces; bitwise equality where the
+arithmetic per point is identical (tile shapes, z chunks, resume, mirror images,
+power-of-two source scaling)."""
+
+import numpy as np
+import pytest
+
+import workloads
+from gpu_util import rel_l2, run_gpu, say
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f32": 1e-4, "f64": 1e-11}
+
+
+def _smooth(rng, shape, passes=4):
+    f = rng.standard_normal(shape)
+    for ax in range(len(shape)):
+        for _ in range(passes):
+            f = 0.25 * np.roll(f, 1, ax) + 0.5 * f + 0.25 * np.roll(f, -1, ax)
+    return f
+
+
+def _receivers_3d(shape, z):
+    nz, ny, nx = shape
+    plane = [(x, y, z) for y in range(0, ny, 3) for x in range(0, nx, 3)]
+    well = [(nx // 3, ny // 2, k) for k in range(nz)]          # many events in one column
+    corners = [(0, 0, 0), (nx - 1, ny - 1, nz - 1), (nx - 1, 0, nz - 1), (0, ny - 1, 0)]
+    return np.array(plane + well + corners, dtype=np.int64)
+
+
+# ----------------------------------------------------------------------------- Ricker
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_ricker_samples_match_oracle(oracle_mod, dtype):
+    import torch
+
+    from paper_1410_1387_amd import fdwave as F
+
+    tdt = torch.float32 if dtype == "f32" else torch.float64
+    dt = 6.9e-4
+    out = torch.empty(3000, dtype=tdt, device="cuda")
+    say(f"fd_ricker {dtype}")
+    F.fd_ricker(out, dt, 15.0, 0.1, None)
+    torch.cuda.synchronize()
+    ref = oracle_mod.ricker(3000, dt, 15.0, 0.1)
+    err = np.abs(out.double().cpu().numpy() - ref).max()
+    assert err <= (1e-7 if dtype == "f32" else 1e-15), err
+
+
+# ----------------------------------------------------------------------------- small 3-D, every radius
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("r", [1, 2, 3, 4, 5, 6, 7, 8])
+def test_small_3d_every_radius(oracle_mod, r, dtype):
+    # 70 x 37 x 23: two x tiles and three y tiles, both ragged, several z chunks
+    shape = (23, 37, 70)
+    h, T = 10.0, 80
+    v = workloads.layered_velocity(shape, seed=r)
+    dt = 0.5 * oracle_mod.dt_max(3, r, h, v.max())
+    rng = np.random.default_rng(100 + r)
+    wav2 = rng.standard_normal(T)
+    s1, s2 = (35, 18, 11), (0, 36, 22)  # interior and a corner
+    rec = _receivers_3d(shape, 3)
+    got = run_gpu(v, r, h, dt, T, dtype, sources=[(s2, wav2)], receivers=rec, ricker=(s1, 30.0, 0.04),
+                  label="small3d")
+    ref = oracle_mod.forward(v, h, dt, r, T, [(s1, oracle_mod.ricker(T, dt, 30.0, 0.04)), (s2, wav2)], rec)
+    eu, ep, et = rel_l2(got["u"], ref["u"]), rel_l2(got["u_prev"], ref["u_prev"]), rel_l2(got["traces"], ref["traces"])
+    say(f"r={r} {dtype}: rel L2 u {eu:.2e} u_prev {ep:.2e} traces {et:.2e} [{got['config']}]")
+    assert got["step"] == T
+    assert eu <= TOL[dtype] and ep <= TOL[dtype] and et <= TOL[dtype]
+
+
+# ----------------------------------------------------------------------------- 2-D
+
+
+def test_2d_256_fp64_workload(oracle_mod):
+    # 256 x 256, h = 10, r = 4, FP64, v = 2000, dt = 0.5 CFL, Ricker 15 Hz at the centre,
+    # zero boundaries, 500 steps, receiver line at row 32
+    shot = workloads.c1_2d_fp64()
+    v = shot.velocity()
+    dt = shot.courant * oracle_mod.dt_max(2, shot.r, shot.h, v.max())
+    got = run_gpu(v, shot.r, shot.h, dt, shot.nsteps, "f64", receivers=shot.receivers,
+                  ricker=(shot.source, shot.f0, 1.5 / shot.f0), label="2d_256_fp64")
+    ref = oracle_mod.forward(v, shot.h, dt, shot.r, shot.nsteps,
+                             [(shot.source, oracle_mod.ricker(shot.nsteps, dt, shot.f0))], shot.receivers)
+    eu, et = rel_l2(got["u"], ref["u"]), rel_l2(got["traces"], ref["traces"])
+    say(f"2d fp64: rel L2 u {eu:.2e} traces {et:.2e}")
+    assert eu <= 1e-11 and et <= 1e-11
+
+
+@pytest.mark.parametrize("dtype,r", [("f32", 2), ("f32", 8), ("f64", 3)])
+def test_2d_ragged(oracle_mod, dtype, r):
+    shape = (157, 300)  # (ny, nx): ragged against the 256/128-wide 2-D tiles
+    h, T = 5.0, 300
+    v = workloads.layered_velocity(shape, seed=7)
+    dt = 0.45 * oracle_mod.dt_max(2, r, h, v.max())
+    rec = np.array([(x, 5) for x in range(0, 300, 7)] + [(299, 156), (0, 0)])
+    got = run_gpu(v, r, h, dt, T, dtype, receivers=rec, ricker=((150, 80), 25.0, 0.04), label="2d ragged")
+    ref = oracle_mod.forward(v, h, dt, r, T, [((150, 80), oracle_mod.ricker(T, dt, 25.0, 0.04))], rec)
+    eu, et = rel_l2(got["u"], ref["u"]), rel_l2(got["traces"], ref["traces"])
+    say(f"2d {dtype} r={r}: rel L2 u {eu:.2e} traces {et:.2e}")
+    assert eu <= TOL[dtype] and et <= TOL[dtype]
+
+
+# ----------------------------------------------------------------------------- long FP32 run
+
+
+def test_fp32_long_run_layered(oracle_mod):
+    # 1000 steps: FP32 rounding accumulates over the whole run
+    shape, r, h, T = (96, 96, 96), 4, 10.0, 1000
+    v = workloads.layered_velocity(shape, seed=3)
+    dt = 0.5 * oracle_mod.dt_max(3, r, h, v.max())
+    rec = workloads.surface_receivers(96, 96, 3, 4)
+    got = run_gpu(v, r, h, dt, T, "f32", receivers=rec, ricker=((48, 48, 3), 15.0, 1.5 / 15), label="long f32")
+    ref = oracle_mod.forward(v, h, dt, r, T, [((48, 48, 3), oracle_mod.ricker(T, dt, 15.0))], rec)
+    eu, et = rel_l2(got["u"], ref["u"]), rel_l2(got["traces"], ref["traces"])
+    say(f"96^3 x 1000 f32: rel L2 u {eu:.2e} traces {et:.2e}")
+    assert eu <= 1e-4 and et <= 1e-4
+
+
+# ----------------------------------------------------------------------------- full-size grids
+
+
+def _full_grid_case(oracle_mod, shot, T, seed):
+    v = shot.velocity()
+    dt = shot.courant * oracle_mod.dt_max(3, shot.r, shot.h, v.max())
+    rng = np.random.default_rng(seed)
+    u0 = _smooth(rng, shot.shape, 2)
+    um1 = 0.99 * u0
+    got = run_gpu(v, shot.r, shot.h, dt, T, "f32", receivers=shot.receivers, u0=u0, um1=um1,
+                  ricker=(shot.source, shot.f0, 0.0), label=shot.name)
+    ref = oracle_mod.forward(v, shot.h, dt, shot.r, T, [(shot.source, oracle_mod.ricker(T, dt, shot.f0, 0.0))],
+                             shot.receivers, u0=u0, um1=um1)
+    eu, et = rel_l2(got["u"], ref["u"]), rel_l2(got["traces"], ref["traces"])
+    say(f"{shot.name} x {T}: rel L2 u {eu:.2e} traces {et:.2e} [{got['config']}]")
+    assert eu <= 1e-4 and et <= 1e-4
+
+
+def test_full_grid_512_r4(oracle_mod):
+    # the benchmark's grid and launch configuration, every point active from a random start
+    _full_grid_case(oracle_mod, workloads.c2_3d_layered(), 20, 21)
+
+
+def test_full_grid_384_r8(oracle_mod):
+    _full_grid_case(oracle_mod, workloads.c3_3d_noise(), 16, 22)
+
+
+# ----------------------------------------------------------------------------- bitwise invariances
+
+
+@pytest.mark.parametrize("dtype,r,ncfg", [("f32", 4, 7), ("f32", 8, 7), ("f64", 4, 3)])
+def test_tile_shapes_bitwise(oracle_mod, dtype, r, ncfg):
+    # the per-point arithmetic does not depend on the tile shape or z chunk: any
+    # difference would expose a race or an indexing error
+    shape, h, T = (41, 45, 77), 10.0, 30
+    v = workloads.layered_velocity(shape, seed=9)
+    dt = 0.5 * oracle_mod.dt_max(3, r, h, v.max())
+    rng = np.random.default_rng(5)
+    u0 = _smooth(rng, shape)
+    rec = _receivers_3d(shape, 7)
+    base = run_gpu(v, r, h, dt, T, dtype, receivers=rec, u0=u0, um1=0.5 * u0, ricker=((20, 20, 20), 30.0, 0.0),
+                   tuning=(0, 0), label="tile base")
+    runs = [(c, 0) for c in range(1, ncfg)] + [(0, 5), (0, 8), (0, 41)]
+    for cfg in runs:
+        got = run_gpu(v, r, h, dt, T, dtype, receivers=rec, u0=u0, um1=0.5 * u0, ricker=((20, 20, 20), 30.0, 0.0),
+                      tuning=cfg, label=f"tile {cfg}")
+        assert np.array_equal(got["u"], base["u"]), (cfg, got["config"])
+        assert np.array_equal(got["traces"], base["traces"]), cfg
+
+
+def test_mirror_symmetry_bitwise(oracle_mod):
+    n, r, h, T = 31, 4, 10.0, 90
+    v = np.full((n, n, n), 2500.0)
+    dt = 0.5 * oracle_mod.dt_max(3, r, h, 2500.0)
+    got = run_gpu(v, r, h, dt, T, "f32", ricker=((15, 15, 15), 40.0, 0.02), label="mirror")
+    u = got["u"]
+    assert np.abs(u).max() > 0
+    for ax in range(3):
+        assert np.array_equal(u, np.flip(u, ax)), ax
+
+
+def test_amplitude_power_of_two_bitwise(oracle_mod):
+    import torch
+
+    from paper_1410_1387_amd import Propagator
+
+    shape, r, h, T = (20, 24, 28), 4, 10.0, 60
+    v = workloads.layered_velocity(shape, seed=1)
+    dt = 0.5 * oracle_mod.dt_max(3, r, h, v.max())
+    outs = []
+    for amp in (1.0, 2.0 ** 20):
+        say(f"amp {amp}")
+        p = Propagator(torch.tensor(v, dtype=torch.float32, device="cuda"), r, h, dt, "f32", max_sources=1)
+        p.inject(p.ricker(T, 30.0, 0.03), (14, 12, 10), amp=amp)
+        p.step(T)
+        outs.append(p.state()[0].cpu().numpy().astype(np.float64))
+        p.close()
+    assert np.array_equal(outs[1], outs[0] * 2.0 ** 20)
+
+
+def test_resume_bitwise(oracle_mod):
+    import torch
+
+    from paper_1410_1387_amd import Propagator
+
+    shape, r, h, T, T1 = (30, 33, 70), 4, 10.0, 60, 23
+    v = workloads.layered_velocity(shape, seed=2)
+    dt = 0.5 * oracle_mod.dt_max(3, r, h, v.max())
+    rec = _receivers_3d(shape, 4)
+    vt = torch.tensor(v, dtype=torch.float32, device="cuda")
+
+    def make():
+        p = Propagator(vt, r, h, dt, "f32", max_sources=1, max_receivers=len(rec))
+        p.inject(p.ricker(T, 25.0, 0.04), (33, 16, 15))
+        return p
+
+    say("resume: straight run")
+    a = make()
+    tra = a.record(rec, T)
+    a.step(T)
+    ua = a.state()[0].cpu().numpy()
+    tra = tra.cpu().numpy()
+    say("resume: split run")
+    b = make()
+    trb1 = b.record(rec, T1)
+    b.step(T1)
+    u, up, n = b.state()
+    trb1 = trb1.cpu().numpy()
+    c = make()
+    c.set_state(u, up, n)
+    trc = c.record(rec, T - T1)
+    c.step(T - T1)
+    uc = c.state()[0].cpu().numpy()
+    assert np.array_equal(ua, uc)
+    assert np.array_equal(tra, np.concatenate([trb1, trc.cpu().numpy()]))
+    for p in (a, b, c):
+        p.close()
+
+
+# ----------------------------------------------------------------------------- periodic closed form
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-10), ("f32", 2e-5)])
+def test_periodic_standing_wave(oracle_mod, dtype, tol):
+    import math
+
+    shape, r, h, v0 = (24, 20, 32), 4, 10.0, 2000.0
+    dt = 0.8 * oracle_mod.dt_max(3, r, h, v0)
+    w = [float(x) for x in oracle_mod.weights(r)]
+    axes, kap2 = [], 0.0
+    for a, m in enumerate([1, 2, 1]):
+        n_a = shape[::-1][a]
+        k = 2 * math.pi * m / (n_a * h)
+        axes.append(np.sin(k * np.arange(n_a) * h + 0.3))
+        kap2 -= (w[0] + 2 * sum(w[l] * math.cos(l * k * h) for l in range(1, r + 1))) / h ** 2
+    phi = np.multiply.outer(axes[2], np.multiply.outer(axes[1], axes[0]))
+    cw = 1 - dt * dt * v0 * v0 * kap2 / 2
+    T = 400
+    got = run_gpu(np.full(shape, v0), r, h, dt, T, dtype, bc="periodic", u0=phi, um1=cw * phi, label="standing")
+    expect = math.cos(math.acos(cw) * T) * phi
+    err = np.abs(got["u"] - expect).max()
+    say(f"standing wave {dtype}: max err {err:.2e}")
+    assert err <= tol
+
+
+# ----------------------------------------------------------------------------- edge cases and errors
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 1), (3, 2, 5), (9, 1, 4), (2, 70, 1)])
+def test_tiny_and_degenerate_grids(oracle_mod, shape):
+    r, h, T = 4, 10.0, 25
+    v = 1500 + 100 * np.arange(np.prod(shape)).reshape(shape) % 700
+    v = v.astype(np.float64)
+    dt = 0.5 * oracle_mod.dt_max(3, r, h, v.max())
+    src = (shape[2] // 2, shape[1] // 2, shape[0] // 2)
+    rec = np.array([(x, y, z) for z in range(shape[0]) for y in range(shape[1]) for x in range(shape[2])])
+    rng = np.random.default_rng(3)
+    wav = rng.standard_normal(T)
+    got = run_gpu(v, r, h, dt, T, "f64", sources=[(src, wav)], receivers=rec, label=f"tiny {shape}")
+    ref = oracle_mod.forward(v, h, dt, r, T, [(src, wav)], rec)
+    assert rel_l2(got["u"], ref["u"]) <= 1e-11 and rel_l2(got["traces"], ref["traces"]) <= 1e-11
+
+
+def test_error_paths_leave_state_untouched(oracle_mod):
+    import torch
+
+    from paper_1410_1387_amd import Propagator
+    from paper_1410_1387_amd import fdwave as F
+
+    shape, r, h = (12, 14, 16), 4, 10.0
+    v = torch.full(shape, 3000.0, device="cuda")
+    dtm = oracle_mod.dt_max(3, r, h, 3000.0)
+    say("error paths")
+    with pytest.raises(F.FdError) as e:
+        Propagator(v, r, h, 1.01 * dtm)
+    assert e.value.status == F.FD_E_UNSTABLE
+    with pytest.raises(F.FdError) as e:
+        Propagator(-v, r, h, 0.5 * dtm)
+    assert e.value.status == F.FD_E_INVAL
+    with pytest.raises(F.FdError) as e:
+        Propagator(v, 9, h, 0.5 * dtm)
+    assert e.value.status == F.FD_E_INVAL
+    p = Propagator(v, r, h, 0.5 * dtm, max_sources=1, max_receivers=2)
+    wav = p.ricker(10, 30.0, 0.0)
+    with pytest.raises(F.FdError) as e:
+        p.inject(wav, (16, 0, 0))
+    assert e.value.status == F.FD_E_RANGE
+    p.inject(wav, (8, 7, 6))
+    with pytest.raises(F.FdError) as e:
+        p.inject(wav, (1, 1, 1))  # max_sources = 1
+    assert e.value.status == F.FD_E_RANGE
+    with pytest.raises(F.FdError) as e:
+        p.record([(0, 0, 0)] * 3, 5)  # max_receivers = 2
+    assert e.value.status == F.FD_E_RANGE
+    with pytest.raises(F.FdError):
+        p.record([(0, 0, 12)], 5)  # z outside
+    p.record([(8, 7, 6), (0, 0, 0)], 5)
+    p.step(0)
+    p.step(5)
+    u5 = p.state()[0].clone()
+    with pytest.raises(F.FdError) as e:
+        p.step(1)  # trace capacity 5 reached: rejected before any launch
+    assert e.value.status == F.FD_E_RANGE
+    assert p.step_count == 5
+    assert torch.equal(p.state()[0], u5)
+    p.sync()
+    p.close()
