@@ -1,0 +1,229 @@
+"""Benchmark: grid-point updates per second of the leapfrog acoustic propagator on
+one MI355X, with the stencil kernel's HBM roofline fraction, and the FP64 oracle
+timed on the host cores beside it.
+
+One bench step is one whole shot of the 3-D workload: 512^3 grid, h = 10 m,
+radius 4 (25-point star), FP32, 8 random layers in [1500, 4500] m/s (seed 0),
+Ricker 15 Hz at (256, 256, 16), 1000 time steps, 128 x 128 surface receivers.
+A shot runs every row of the forward path on the GPU: model preparation
+(c = (v dt / h)^2), Ricker samples, source and receiver registration, and 1000
+stencil launches with the source and receivers fused in.  The velocity model is
+resident in HBM before the timed region starts.
+
+    python bench.py [--steps K] [--warmup W] [--no-cpu] [--gradient] [--serving]
+
+Prints one JSON line.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "fwd_r4_512_traffic.json")
+KERNEL_SOURCES = ["paper_1410_1387_amd/csrc/fd_stencil.h", "paper_1410_1387_amd/csrc/fd_fwd_f32.hip",
+                  "paper_1410_1387_amd/csrc/fd_types.h"]
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken
+    on the kernel source that is built now; otherwise None."""
+    try:
+        with open(PROFILE_TRAFFIC) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_hash") != kernel_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+# --------------------------------------------------------------------------- forward shot
+
+
+def run_forward(args):
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_1410_1387_amd import fdwave as F
+
+    shot = workloads.c2_3d_layered()
+    nz, ny, nx = shot.shape
+    T = shot.nsteps
+    v = torch.tensor(shot.velocity().astype(np.float32), device="cuda")
+    vmax = float(v.max())
+    dt = shot.courant * F.fd_dt_max(3, shot.r, shot.h, vmax)
+    nrec = len(shot.receivers)
+    ws = torch.empty(F.fd_workspace_bytes(shot.shape, shot.r, "f32", 1, nrec), dtype=torch.uint8, device="cuda")
+    wav = torch.empty(T, dtype=torch.float32, device="cuda")
+    traces = torch.empty((T, nrec), dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+    sp = F.stream_ptr(stream)
+
+    def one_shot(ev=None):
+        ctx = F.fd_create(shot.shape, shot.r, shot.h, dt, v, "f32", "zero", ws, 1, nrec, sp)
+        F.fd_ricker(wav, dt, shot.f0, 1.5 / shot.f0, sp)
+        F.fd_inject(ctx, wav, shot.source, 1.0)
+        F.fd_record(ctx, shot.receivers, traces, T)
+        if ev is not None:
+            ev[0].record(stream)
+        F.fd_step(ctx, T)
+        if ev is not None:
+            ev[1].record(stream)
+        F.fd_sync(ctx)
+        cfg = F.fd_kernel_config(ctx)
+        F.fd_destroy(ctx)
+        return cfg
+
+    for _ in range(args.warmup):
+        one_shot()
+    torch.cuda.synchronize()
+    events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        cfg = one_shot(events[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    step_ms = [a.elapsed_time(b) for a, b in events]
+    launch_ms = sum(step_ms) / (args.steps * T)  # average stencil launch duration
+    pts = nx * ny * nz
+    value = pts * T * args.steps / wall / 1e9
+    algo_bytes = 16.0 * pts  # read u^n, u^{n-1}, c and write u^{n+1}, FP32
+    achieved = algo_bytes / (launch_ms * 1e-3) / 1e9
+    tr = measured_traffic()
+    finite = bool(torch.isfinite(traces).all().item())
+    log(f"forward: {value:.1f} Gpts/s per shot incl. setup; stencil {launch_ms * 1e3:.1f} us/launch, "
+        f"{achieved:.0f} GB/s algorithmic ({cfg}); traces finite={finite}")
+    return {
+        "value": value,
+        "ms_per_step": wall / args.steps * 1e3,
+        "config": {
+            "workload": shot.name, "grid": [nx, ny, nz], "radius": shot.r, "h_m": shot.h, "dt_s": dt,
+            "time_steps_per_shot": T, "velocity": "8 layers U[1500,4500] m/s seed 0",
+            "source": list(shot.source), "receivers": nrec, "shots_per_step": 1, "kernel": cfg,
+        },
+        "roofline": {
+            "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None if tr is None else round(tr / (launch_ms * 1e-3) / 1e9, 1),
+            "algorithmic_bytes_per_launch": algo_bytes, "launch_us": round(launch_ms * 1e3, 2),
+            "stencil_gpts_per_s": round(pts / (launch_ms * 1e-3) / 1e9, 2),
+        },
+    }
+
+
+# --------------------------------------------------------------------------- CPU baseline
+
+
+def run_cpu_baseline(budget_s: float = 12.0):
+    """The FP64 oracle on the host cores, on a bounded sample of the same workload: the
+    full 512^3 grid and layered model, a few time steps (throughput per step is constant)."""
+    import numpy as np
+
+    import oracle
+    import workloads
+
+    oracle._lib()
+    shot = workloads.c2_3d_layered()
+    v = shot.velocity()
+    dt = shot.courant * oracle.dt_max(3, shot.r, shot.h, v.max())
+    # OpenMP threads the oracle runs with: OMP_NUM_THREADS if set, else one per usable core
+    cores = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or len(os.sched_getaffinity(0))
+    rng = np.random.default_rng(0)
+    u0 = rng.standard_normal(shot.shape)
+    t = time.perf_counter()
+    oracle.forward(v, shot.h, dt, shot.r, 1, [(shot.source, oracle.ricker(1, dt))], u0=u0, um1=u0)
+    t1 = time.perf_counter() - t
+    nsteps = max(2, min(200, int(budget_s / max(t1, 1e-3))))
+    t = time.perf_counter()
+    oracle.forward(v, shot.h, dt, shot.r, nsteps, [(shot.source, oracle.ricker(nsteps, dt))], shot.receivers,
+                   u0=u0, um1=u0)
+    el = time.perf_counter() - t
+    pts = int(np.prod(shot.shape))
+    val = pts * nsteps / el / 1e9
+    log(f"cpu baseline: {val:.3f} Gpts/s ({nsteps} steps of 512^3 FP64 in {el:.1f} s, {cores} threads)")
+    return {"value": round(val, 4), "unit": "Gpts/s", "cores": cores, "kind": "oracle",
+            "sample": f"FP64 oracle, full 512^3 grid of the same layered workload, r=4, {nsteps} time steps "
+                      f"({el:.1f} s wall)"}
+
+
+def run_gradient():
+    raise NotImplementedError("gradient workload not built yet")
+
+
+def run_serving():
+    raise NotImplementedError("serving workload not built yet")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3, help="timed shots (each 1000 time steps of 512^3)")
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--gradient", action="store_true", help="also time the adjoint gradient workload")
+    ap.add_argument("--serving", action="store_true", help="also run the shot-serving workload")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is "
+                                   "described but not built)"}))
+        sys.exit(2)
+
+    import torch
+
+    from paper_1410_1387_amd import fdwave as F
+
+    F.lib()  # the HIP library must be present: no fallback
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(2)
+    torch.cuda.set_device(0)
+    fw = run_forward(args)
+    out = {
+        "metric": "grid-point updates/s (Gpts/s), % of HBM roofline; p50/p99 shot latency",
+        "value": round(fw["value"], 2),
+        "unit": "Gpts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(fw["ms_per_step"], 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": fw["config"],
+        "roofline": fw["roofline"],
+    }
+    if args.gradient:
+        out["gradient"] = run_gradient()
+    if args.serving:
+        out["serving"] = run_serving()
+    out["cpu_baseline"] = None if args.no_cpu else run_cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,6 +1,6 @@
 // fd_adj_f32.hip -- explicit instantiations of the adjoint stencil kernels for float
 // and the (radius, ndim) -> tile-configuration table the host side dispatches on.
-// The lists below are the tile shapes this file instantiates.
+// Written by gen_registry.py; edit the tile lists there.
 #include "fd_stencil.h"
 
 namespace fdw {

@@ -22,6 +22,11 @@
 
 using namespace fdw;
 
+// Byte offset of each row's interior: a multiple of the 128-byte cache line.
+#ifndef FD_ROW_ALIGN_BYTES
+#define FD_ROW_ALIGN_BYTES 128
+#endif
+
 // ------------------------------------------------------------------ errors
 
 static thread_local std::string g_last_error;
@@ -78,12 +83,12 @@ bool make_layout(const fd_grid *g, int r, fd_dtype dt, int64_t max_src, int64_t 
     L->ndim = g->ndim;
     L->r = r;
     L->esize = dt == FD_F32 ? 4 : 8;
-    const int64_t xo = 64 / (int64_t)L->esize;  // interior starts 64 bytes into each row
+    const int64_t xo = FD_ROW_ALIGN_BYTES / (int64_t)L->esize;  // interior starts on a cache line
     L->knx = g->n[0];
     L->kny = g->ndim == 3 ? g->n[1] : 1;
     L->knz = g->ndim == 3 ? g->n[2] : g->n[1];
     if (L->knx > (1 << 30) || L->kny > (1 << 30) || L->knz > (1 << 30)) return false;
-    L->px = align_up(xo + align_up(L->knx, 256) + 16, 256 / (int64_t)L->esize);
+    L->px = align_up(xo + align_up(L->knx, 256) + 16, 128 / (int64_t)L->esize);
     L->py = g->ndim == 3 ? r + align_up(L->kny, 64) + r : 1;
     L->planes = L->knz + 2 * r;
     L->pxy = L->px * L->py;
@@ -92,6 +97,8 @@ bool make_layout(const fd_grid *g, int r, fd_dtype dt, int64_t max_src, int64_t 
     L->field_bytes = (size_t)align_up(L->elems * (int64_t)L->esize, 256);
     L->ncol = L->knx * L->kny;
     if (L->ncol + 1 > INT32_MAX || max_src + max_rec > INT32_MAX / 2) return false;
+    // kernels address a plane with 32-bit byte offsets
+    if (L->pxy * (int64_t)L->esize >= ((int64_t)1 << 31)) return false;
     size_t o = 0;
     L->o_desc = o;
     o += align_up(sizeof(ShotDesc), 256);
@@ -146,11 +153,12 @@ const AdjEntry *adj_table(fd_dtype dt, int r, int ndim)
     return dt == FD_F32 ? adj_config_f32(r, ndim) : adj_config_f64(r, ndim);
 }
 
-// Planes per z chunk: enough workgroups to fill 256 CUs several times over, but at
-// least 4r planes per chunk so the 2r-plane prologue stays a small overhead.
+// Planes per z chunk: about two workgroups per CU (256 CUs) resident in one wave of
+// the grid, but at least 4r planes per chunk so the 2r-plane prologue (planes a
+// chunk re-reads from its neighbour) stays a small overhead.
 int choose_zch(int64_t tiles_xy, int64_t nz, int r)
 {
-    const int64_t target_wgs = 2048;
+    const int64_t target_wgs = 512;
     int64_t chunks = (target_wgs + tiles_xy - 1) / tiles_xy;
     chunks = std::min<int64_t>(chunks, std::max<int64_t>(1, nz / (4 * r)));
     chunks = std::max<int64_t>(1, chunks);

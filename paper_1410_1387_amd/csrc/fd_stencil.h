@@ -35,6 +35,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+#include <utility>
+
 #include "fd_types.h"
 
 #pragma clang fp contract(off)
@@ -144,6 +147,19 @@ __device__ __forceinline__ int xcd_remap(int b, int G)
     return (xcd < rem) ? xcd * (q + 1) + idx : rem * (q + 1) + (xcd - rem) * q + idx;
 }
 
+// Calls f(integral_constant<int, 0>) ... f(integral_constant<int, N-1>): the index is a
+// compile-time constant inside f whatever the loop unroller decides.
+template <class F, int... I>
+__device__ __forceinline__ void static_for_impl(F &&f, std::integer_sequence<int, I...>)
+{
+    (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void static_for(F &&f)
+{
+    static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
 __device__ __forceinline__ int lower_bound_z(const Event *ev, int lo, int hi, int z)
 {
     while (lo < hi) {
@@ -182,6 +198,10 @@ struct TileCfg {
     static constexpr int NH = NHY + NHX;
     static constexpr int HPT = (NH + NT - 1) / NT;         // halo vectors per thread
     static constexpr int YR = EY + 2 * HY;                 // rows a thread touches along y
+    // forward kernel: halo fetched HOFF planes ahead into a ring of NB LDS plane buffers
+    // (early halo for R <= 4; larger radii would need too much LDS)
+    static constexpr int HOFF = (R <= 4) ? R : 0;
+    static constexpr int NB = HOFF + 2;
     static_assert(256 % BX == 0 && 64 % BY == 0, "tile must divide the layout alignment");
 };
 
@@ -259,6 +279,38 @@ __device__ __forceinline__ int next_event(const ShotDesc &s, const TileGeom<C> &
 
 // ------------------------------------------------------------------ forward step
 
+// Byte address of element byte-offset `ob` inside plane z of a padded field whose
+// first ghost plane starts at `base` (plane pitch pxy elements).  The plane base is
+// uniform across the workgroup, the in-plane offset is a 32-bit per-lane value.
+template <typename T>
+__device__ __forceinline__ const T *plane_at(const T *base, int64_t pxy, int zp, uint32_t ob)
+{
+    return reinterpret_cast<const T *>(reinterpret_cast<const char *>(base + (int64_t)zp * pxy) + ob);
+}
+template <typename T>
+__device__ __forceinline__ T *plane_at(T *base, int64_t pxy, int zp, uint32_t ob)
+{
+    return reinterpret_cast<T *>(reinterpret_cast<char *>(base + (int64_t)zp * pxy) + ob);
+}
+
+// One leapfrog step over this workgroup's tile and z chunk.
+//
+// The z register queue has P = 2R+2 slots: planes z-R .. z+R of the current plane
+// z plus one slot receiving plane z+R+1 while z is computed; it shifts by one slot
+// per plane.  (Unrolling the plane loop by P to rotate the queue instead removes the
+// register moves but multiplies the code size, and measured slower on gfx950.)
+//
+// Halo timing: the x/y halo of a plane is interior data of the neighbouring tiles.
+// With HOFF = R the halo of plane z+R+1 is fetched in the same iteration in which
+// the neighbours fetch that plane as their queue tail, so the requests meet in L2,
+// and it waits in a ring of NB = R+2 LDS plane buffers until the plane becomes the
+// centre.  (Fetching it only when it is needed comes R planes later, by which time
+// the XCD has streamed several MB and the lines have left its 4 MB L2.)  Plane p
+// lives in buffer p mod NB: when iteration z writes the halo of plane z+R its buffer
+// was last read by iteration z-2, and every thread passed the barrier of z-1.
+//
+// The plane loop is unrolled by 2 (static_for) so that the u^{n-1}, c and halo
+// prefetch registers alternate between two sets by parity.
 template <class C>
 __device__ __forceinline__ void fwd_tile(const ShotDesc &s, const typename C::type *__restrict__ cur,
                                          const typename C::type *prev, typename C::type *out,
@@ -267,188 +319,206 @@ __device__ __forceinline__ void fwd_tile(const ShotDesc &s, const typename C::ty
 {
     typedef typename C::type T;
     constexpr int R = C::R, VEC = C::VEC, EY = C::EY, HPT = C::HPT, HY = C::HY;
+    constexpr int P = 2 * R + 2;
+    constexpr int HOFF = C::HOFF, NB = C::NB;
     constexpr StencilWeights<R> W{};
     const T *__restrict__ cc = static_cast<const T *>(s.c);
-    const int64_t px = s.px, pxy = s.pxy;
+    const int64_t pxy = s.pxy;
 
     TileGeom<C> g;
     g.init(s, tx, ty, cz);
     if (g.z0 >= g.z1) return;
 
-    // register queue: q[k] holds u^n at plane z - R + k
-    T q[2 * R + 1][EY][VEC];
+    // in-plane byte offsets (plane index zp = z + R counts the R ghost planes)
+    const int64_t colp = g.col - (int64_t)R * pxy;
+    uint32_t ob[EY];
 #pragma unroll
-    for (int k = 0; k < 2 * R; ++k)
+    for (int e = 0; e < EY; ++e) ob[e] = (uint32_t)((colp + (int64_t)e * s.px) * (int64_t)sizeof(T));
+    uint32_t hob[HPT];
+#pragma unroll
+    for (int k = 0; k < HPT; ++k) hob[k] = (uint32_t)((g.hoff[k] - (int64_t)R * pxy) * (int64_t)sizeof(T));
+
+    T q[P][EY][VEC];
+    T pv[2][EY][VEC], cv[2][EY][VEC], hv[2][HPT][VEC];
+
+    // prologue: planes z0-R .. z0+R into slots 0 .. 2R; u^{n-1} and c of plane z0 into
+    // set 0; halos of planes z0 .. z0+HOFF-1 straight into their LDS buffers and the
+    // halo of plane z0+HOFF into set 0
+#pragma unroll
+    for (int k = 0; k <= 2 * R; ++k)
 #pragma unroll
         for (int e = 0; e < EY; ++e) {
             if (g.lin[e])
-                vld(q[k][e], cur + g.col + e * px + (int64_t)(g.z0 - R + k) * pxy);
+                vld(q[k][e], plane_at(cur, pxy, g.z0 + k, ob[e]));
             else
                 vzero(q[k][e]);
         }
-    // prefetch registers for the plane about to be processed
-    T nu[EY][VEC], npv[EY][VEC], ncc[EY][VEC], nh[HPT][VEC];
-    {
-        const int64_t zo = (int64_t)g.z0 * pxy;
 #pragma unroll
-        for (int e = 0; e < EY; ++e) {
-            if (g.lin[e])
-                vld(nu[e], cur + g.col + e * px + zo + R * pxy);
-            else
-                vzero(nu[e]);
-            if (g.rin[e]) {
-                vld_nt(npv[e], prev + g.col + e * px + zo);
-                vld_nt(ncc[e], cc + g.col + e * px + zo);
-            } else {
-                vzero(npv[e]);
-                vzero(ncc[e]);
-            }
-        }
-#pragma unroll
-        for (int k = 0; k < HPT; ++k) {
-            if (g.hval[k])
-                vld(nh[k], cur + g.hoff[k] + zo);
-            else
-                vzero(nh[k]);
+    for (int e = 0; e < EY; ++e) {
+        if (g.rin[e]) {
+            vld_nt(pv[0][e], plane_at(prev, pxy, g.z0 + R, ob[e]));
+            vld_nt(cv[0][e], plane_at(cc, pxy, g.z0 + R, ob[e]));
+        } else {
+            vzero(pv[0][e]);
+            vzero(cv[0][e]);
         }
     }
-    int nev = next_event<C>(s, g, g.z0);
-
-    int buf = 0;
-    for (int z = g.z0; z < g.z1; ++z) {
-        T pv[EY][VEC], cv[EY][VEC], hv[HPT][VEC];
 #pragma unroll
-        for (int e = 0; e < EY; ++e)
-#pragma unroll
-            for (int v = 0; v < VEC; ++v) {
-                q[2 * R][e][v] = nu[e][v];
-                pv[e][v] = npv[e][v];
-                cv[e][v] = ncc[e][v];
-            }
-#pragma unroll
-        for (int k = 0; k < HPT; ++k)
-#pragma unroll
-            for (int v = 0; v < VEC; ++v) hv[k][v] = nh[k][v];
-
-        if (z + 1 < g.z1) {
-            const int64_t zo = (int64_t)(z + 1) * pxy;
-#pragma unroll
-            for (int e = 0; e < EY; ++e) {
-                if (g.lin[e]) vld(nu[e], cur + g.col + e * px + zo + R * pxy);
-                if (g.rin[e]) {
-                    vld_nt(npv[e], prev + g.col + e * px + zo);
-                    vld_nt(ncc[e], cc + g.col + e * px + zo);
-                }
-            }
+    for (int j = 0; j < HOFF; ++j) {
+        if (g.z0 + j < g.z1) {
+            T *L = lds + ((g.z0 + j) % NB) * C::LDS;
 #pragma unroll
             for (int k = 0; k < HPT; ++k)
-                if (g.hval[k]) vld(nh[k], cur + g.hoff[k] + zo);
-        }
-
-        // stage plane z (interior from the queue, halo from the prefetch) in LDS
-        T *L = lds + buf * C::LDS;
-#pragma unroll
-        for (int e = 0; e < EY; ++e) vst(L + (g.ly + e + HY) * C::LW + C::LPAD + g.lx, q[R][e]);
-#pragma unroll
-        for (int k = 0; k < HPT; ++k)
-            if (g.hval[k]) vst(L + g.hl[k], hv[k]);
-        __syncthreads();
-
-        // y neighbour rows: yr[k] is row ly - HY + k at this thread's x vector
-        T yr[C::YR][VEC];
-#pragma unroll
-        for (int k = 0; k < C::YR; ++k) {
-            if (k >= HY && k < HY + EY) {
-#pragma unroll
-                for (int v = 0; v < VEC; ++v) yr[k][v] = q[R][k - HY][v];
-            } else {
-                vld(yr[k], L + (g.ly + k) * C::LW + C::LPAD + g.lx);
-            }
-        }
-
-        T un[EY][VEC];
-#pragma unroll
-        for (int e = 0; e < EY; ++e) {
-            T xs[C::NXV * VEC];
-#pragma unroll
-            for (int j = 0; j < C::NXV; ++j) {
-                T tmp[VEC];
-                vld(tmp, L + (g.ly + e + HY) * C::LW + g.lx + j * VEC);
-#pragma unroll
-                for (int v = 0; v < VEC; ++v) xs[j * VEC + v] = tmp[v];
-            }
-#pragma unroll
-            for (int v = 0; v < VEC; ++v) {
-                const T u0 = q[R][e][v];
-                T acc = T(0);
-#pragma unroll
-                for (int l = 1; l <= R; ++l)
-                    acc = fma_t(T(W.w[l]), (xs[C::LPAD + v + l] - u0) + (xs[C::LPAD + v - l] - u0), acc);
-                if (C::NDIM == 3) {
-#pragma unroll
-                    for (int l = 1; l <= R; ++l)
-                        acc = fma_t(T(W.w[l]), (yr[HY + e + l][v] - u0) + (yr[HY + e - l][v] - u0), acc);
+                if (g.hval[k]) {
+                    T t[VEC];
+                    vld(t, plane_at(cur, pxy, g.z0 + j + R, hob[k]));
+                    vst(L + g.hl[k], t);
                 }
-#pragma unroll
-                for (int l = 1; l <= R; ++l)
-                    acc = fma_t(T(W.w[l]), (q[R + l][e][v] - u0) + (q[R - l][e][v] - u0), acc);
-                un[e][v] = fma_t(cv[e][v], acc, T(2) * u0 - pv[e][v]);
-            }
         }
+    }
+#pragma unroll
+    for (int k = 0; k < HPT; ++k) {
+        if (g.hval[k] && g.z0 + HOFF < g.z1)
+            vld(hv[0][k], plane_at(cur, pxy, g.z0 + HOFF + R, hob[k]));
+        else
+            vzero(hv[0][k]);
+    }
+    int nev = next_event<C>(s, g, g.z0);
+    int bz = g.z0 % NB;              // LDS buffer of plane z
+    int bh = (g.z0 + HOFF) % NB;     // LDS buffer of plane z + HOFF
 
-        // fused sources (added before the store) and receivers (recorded after them)
-        if (z == nev) {
-            int nxt = 0x7fffffff;
+    for (int zb = g.z0; zb < g.z1; zb += 2) {
+        static_for<2>([&](auto st_) __attribute__((always_inline)) {
+            constexpr int st = decltype(st_)::value;
+            constexpr int cs = st & 1, ns = cs ^ 1;
+            constexpr int tail = 2 * R + 1;  // slot receiving plane z+R+1
+            constexpr int ctr = R;           // slot of plane z
+            const int z = zb + st;
+            if (z >= g.z1) return;
+            if (z + 1 < g.z1) {
 #pragma unroll
-            for (int e = 0; e < EY; ++e) {
-#pragma unroll
-                for (int v = 0; v < VEC; ++v) {
-                    if (g.rin[e] && g.gx + v < s.nx) {
-                        const int cidx = (g.gy + e) * s.nx + g.gx + v;
-                        const int lo = s.ev_ptr[cidx], hi = s.ev_ptr[cidx + 1];
-                        if (lo < hi) {
-                            int p = lower_bound_z(s.ev, lo, hi, z);
-                            for (; p < hi && s.ev[p].z == z; ++p) {
-                                const int code = s.ev[p].code;
-                                if (code < 0) {
-                                    const SourceInfo si = s.src[~code];
-                                    if (step < si.nsamp)
-                                        un[e][v] += T(si.scale) * static_cast<const T *>(si.wav)[step];
-                                } else if (record) {
-                                    const int64_t row = step - s.rec_base;
-                                    if (row >= 0 && row < s.rec_cap)
-                                        static_cast<T *>(s.traces)[row * s.nrec + code] = un[e][v];
-                                }
-                            }
-                            if (p < hi) nxt = min(nxt, s.ev[p].z);
-                        }
+                for (int e = 0; e < EY; ++e) {
+                    if (g.lin[e]) vld(q[tail][e], plane_at(cur, pxy, z + 1 + 2 * R, ob[e]));
+                    if (g.rin[e]) {
+                        vld_nt(pv[ns][e], plane_at(prev, pxy, z + 1 + R, ob[e]));
+                        vld_nt(cv[ns][e], plane_at(cc, pxy, z + 1 + R, ob[e]));
                     }
                 }
             }
-            nev = nxt;
-        }
+            if (z + 1 + HOFF < g.z1) {
+#pragma unroll
+                for (int k = 0; k < HPT; ++k)
+                    if (g.hval[k]) vld(hv[ns][k], plane_at(cur, pxy, z + 1 + HOFF + R, hob[k]));
+            }
 
+            // stage plane z's interior (from the queue) and plane z+HOFF's halo in LDS
+            T *L = lds + bz * C::LDS;
 #pragma unroll
-        for (int e = 0; e < EY; ++e) {
-            if (g.rin[e]) {
-                T *p = out + g.col + e * px + (int64_t)z * pxy;
-                if (g.gx + VEC <= s.nx) {
-                    vst_nt(p, un[e]);
+            for (int e = 0; e < EY; ++e) vst(L + (g.ly + e + HY) * C::LW + C::LPAD + g.lx, q[ctr][e]);
+            if (z + HOFF < g.z1) {
+                T *LH = lds + bh * C::LDS;
+#pragma unroll
+                for (int k = 0; k < HPT; ++k)
+                    if (g.hval[k]) vst(LH + g.hl[k], hv[cs][k]);
+            }
+            __syncthreads();
+
+            // y neighbour rows: yr[k] is row ly - HY + k at this thread's x vector
+            T yr[C::YR][VEC];
+#pragma unroll
+            for (int k = 0; k < C::YR; ++k) {
+                if (k >= HY && k < HY + EY) {
+#pragma unroll
+                    for (int v = 0; v < VEC; ++v) yr[k][v] = q[ctr][k - HY][v];
                 } else {
-#pragma unroll
-                    for (int v = 0; v < VEC; ++v)
-                        if (g.gx + v < s.nx) p[v] = un[e][v];
+                    vld(yr[k], L + (g.ly + k) * C::LW + C::LPAD + g.lx);
                 }
             }
-        }
+
+            T un[EY][VEC];
+#pragma unroll
+            for (int e = 0; e < EY; ++e) {
+                T xs[C::NXV * VEC];
+#pragma unroll
+                for (int j = 0; j < C::NXV; ++j) {
+                    T tmp[VEC];
+                    vld(tmp, L + (g.ly + e + HY) * C::LW + g.lx + j * VEC);
+#pragma unroll
+                    for (int v = 0; v < VEC; ++v) xs[j * VEC + v] = tmp[v];
+                }
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) {
+                    const T u0 = q[ctr][e][v];
+                    T acc = T(0);
+#pragma unroll
+                    for (int l = 1; l <= R; ++l)
+                        acc = fma_t(T(W.w[l]), (xs[C::LPAD + v + l] - u0) + (xs[C::LPAD + v - l] - u0), acc);
+                    if (C::NDIM == 3) {
+#pragma unroll
+                        for (int l = 1; l <= R; ++l)
+                            acc = fma_t(T(W.w[l]), (yr[HY + e + l][v] - u0) + (yr[HY + e - l][v] - u0), acc);
+                    }
+#pragma unroll
+                    for (int l = 1; l <= R; ++l)
+                        acc = fma_t(T(W.w[l]), (q[R + l][e][v] - u0) + (q[R - l][e][v] - u0), acc);
+                    un[e][v] = fma_t(cv[cs][e][v], acc, T(2) * u0 - pv[cs][e][v]);
+                }
+            }
+
+            // fused sources (added before the store) and receivers (recorded after them)
+            if (z == nev) {
+                int nxt = 0x7fffffff;
+#pragma unroll
+                for (int e = 0; e < EY; ++e) {
+#pragma unroll
+                    for (int v = 0; v < VEC; ++v) {
+                        if (g.rin[e] && g.gx + v < s.nx) {
+                            const int cidx = (g.gy + e) * s.nx + g.gx + v;
+                            const int lo = s.ev_ptr[cidx], hi = s.ev_ptr[cidx + 1];
+                            if (lo < hi) {
+                                int p = lower_bound_z(s.ev, lo, hi, z);
+                                for (; p < hi && s.ev[p].z == z; ++p) {
+                                    const int code = s.ev[p].code;
+                                    if (code < 0) {
+                                        const SourceInfo si = s.src[~code];
+                                        if (step < si.nsamp)
+                                            un[e][v] += T(si.scale) * static_cast<const T *>(si.wav)[step];
+                                    } else if (record) {
+                                        const int64_t row = step - s.rec_base;
+                                        if (row >= 0 && row < s.rec_cap)
+                                            static_cast<T *>(s.traces)[row * s.nrec + code] = un[e][v];
+                                    }
+                                }
+                                if (p < hi) nxt = min(nxt, s.ev[p].z);
+                            }
+                        }
+                    }
+                }
+                nev = nxt;
+            }
 
 #pragma unroll
-        for (int k = 0; k < 2 * R; ++k)
+            for (int e = 0; e < EY; ++e) {
+                if (g.rin[e]) {
+                    T *p = plane_at(out, pxy, z + R, ob[e]);
+                    if (g.gx + VEC <= s.nx) {
+                        vst_nt(p, un[e]);
+                    } else {
 #pragma unroll
-            for (int e = 0; e < EY; ++e)
+                        for (int v = 0; v < VEC; ++v)
+                            if (g.gx + v < s.nx) p[v] = un[e][v];
+                    }
+                }
+            }
 #pragma unroll
-                for (int v = 0; v < VEC; ++v) q[k][e][v] = q[k + 1][e][v];
-        buf ^= 1;
+            for (int k = 0; k < P - 1; ++k)
+#pragma unroll
+                for (int e = 0; e < EY; ++e)
+#pragma unroll
+                    for (int v = 0; v < VEC; ++v) q[k][e][v] = q[k + 1][e][v];
+            bz = (bz + 1 == NB) ? 0 : bz + 1;
+            bh = (bh + 1 == NB) ? 0 : bh + 1;
+        });
     }
 }
 
@@ -456,7 +526,7 @@ template <class C>
 __global__ __launch_bounds__(C::NT) void fwd_kernel(LaunchArgs a)
 {
     typedef typename C::type T;
-    __shared__ __attribute__((aligned(16))) T lds[2 * C::LDS];
+    __shared__ __attribute__((aligned(16))) T lds[C::NB * C::LDS];
     int wg = blockIdx.x;
     if (a.xcd_remap) wg = xcd_remap(wg, (int)gridDim.x);
     int shot = 0, local = wg;

@@ -1,0 +1,88 @@
+"""Writes the kernel-registry translation units fd_fwd_{f32,f64}.hip and
+fd_adj_{f32,f64}.hip: explicit template instantiations of the stencil kernels and the
+(radius, ndim) -> tile-configuration tables the host side dispatches on.
+
+Tile shapes are (threads along x, threads along y, rows per thread); the first entry
+of each list is the default.  Rerun after editing the lists:
+    python paper_1410_1387_amd/csrc/gen_registry.py
+"""
+
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+# 3-D forward tile shapes.  Radii in SWEEP_RADII get every shape; others the default.
+F32_3D = [(16, 16, 2), (32, 8, 2), (16, 8, 4), (16, 32, 2), (32, 16, 2), (16, 16, 1), (8, 32, 2)]
+# radii above 4 keep one row per thread: two rows exceed 256 VGPRs and spill
+F32_3D_BIG_R = [(16, 16, 1), (32, 8, 1), (16, 32, 1), (32, 16, 1)]
+F64_3D = [(32, 16, 1), (32, 8, 2), (16, 16, 2)]
+F32_SWEEP_RADII = {4, 8}
+F64_SWEEP_RADII = {4}
+F2D = (64, 1, 1)          # 2-D forward and adjoint: one row of 64 threads
+ADJ_F32_3D = (16, 16, 1)
+ADJ_F64_3D = (32, 8, 1)
+
+HDR = """// {fname} -- explicit instantiations of the {what} stencil kernels for {T}
+// and the (radius, ndim) -> tile-configuration table the host side dispatches on.
+// Written by gen_registry.py; edit the tile lists there.
+#include "fd_stencil.h"
+
+namespace fdw {{
+"""
+
+
+def cfgname(T, R, nd, txn, tyn, ey):
+    vec = 4 if T == "float" else 2
+    bx = txn * vec
+    by = tyn * ey if nd == 3 else 1
+    nt = txn * (tyn if nd == 3 else 1)
+    return f"{'f32' if T == 'float' else 'f64'} r{R} {nd}d tile {bx}x{by} ({nt} thr, {ey if nd == 3 else 1} row/thr)"
+
+
+def fwd_file(T, sweep3d, sweep_radii, sweep3d_big_r=None):
+    tag = "f32" if T == "float" else "f64"
+    out = HDR.format(fname=f"fd_fwd_{tag}.hip", what="forward", T=T)
+    for R in range(1, 9):
+        lst = sweep3d_big_r if (sweep3d_big_r and R > 4) else sweep3d
+        cfgs3 = lst if R in sweep_radii else lst[:1]
+        out += f"static const FwdEntry k3_r{R}[] = {{\n"
+        for (txn, tyn, ey) in cfgs3:
+            out += f'    fwd_entry<TileCfg<{T}, {R}, 3, {txn}, {tyn}, {ey}>>("{cfgname(T, R, 3, txn, tyn, ey)}"),\n'
+        out += "};\n"
+        txn = F2D[0]
+        out += f"static const FwdEntry k2_r{R}[] = {{\n"
+        out += f'    fwd_entry<TileCfg<{T}, {R}, 2, {txn}, 1, 1>>("{cfgname(T, R, 2, txn, 1, 1)}"),\n'
+        out += "};\n"
+    out += "\nconst FwdEntry *fwd_configs_" + tag + "(int r, int ndim, int *count)\n{\n    switch (r * 10 + ndim) {\n"
+    for R in range(1, 9):
+        for nd in (2, 3):
+            out += f"    case {R * 10 + nd}: *count = (int)(sizeof(k{nd}_r{R}) / sizeof(FwdEntry)); return k{nd}_r{R};\n"
+    out += "    default: *count = 0; return nullptr;\n    }\n}\n\n}  // namespace fdw\n"
+    with open(os.path.join(HERE, f"fd_fwd_{tag}.hip"), "w") as f:
+        f.write(out)
+
+
+def adj_file(T, d3):
+    tag = "f32" if T == "float" else "f64"
+    out = HDR.format(fname=f"fd_adj_{tag}.hip", what="adjoint", T=T)
+    for R in range(1, 9):
+        txn, tyn, ey = d3
+        out += (f"static const AdjEntry a3_r{R} = adj_entry<TileCfg<{T}, {R}, 3, {txn}, {tyn}, {ey}>>"
+                f'("{cfgname(T, R, 3, txn, tyn, ey)}");\n')
+        txn = F2D[0]
+        out += (f"static const AdjEntry a2_r{R} = adj_entry<TileCfg<{T}, {R}, 2, {txn}, 1, 1>>"
+                f'("{cfgname(T, R, 2, txn, 1, 1)}");\n')
+    out += "\nconst AdjEntry *adj_config_" + tag + "(int r, int ndim)\n{\n    switch (r * 10 + ndim) {\n"
+    for R in range(1, 9):
+        for nd in (2, 3):
+            out += f"    case {R * 10 + nd}: return &a{nd}_r{R};\n"
+    out += "    default: return nullptr;\n    }\n}\n\n}  // namespace fdw\n"
+    with open(os.path.join(HERE, f"fd_adj_{tag}.hip"), "w") as f:
+        f.write(out)
+
+
+if __name__ == "__main__":
+    fwd_file("float", F32_3D, F32_SWEEP_RADII, F32_3D_BIG_R)
+    fwd_file("double", F64_3D, F64_SWEEP_RADII)
+    adj_file("float", ADJ_F32_3D)
+    adj_file("double", ADJ_F64_3D)

@@ -154,7 +154,7 @@ def test_full_grid_384_r8(oracle_mod):
 # ----------------------------------------------------------------------------- bitwise invariances
 
 
-@pytest.mark.parametrize("dtype,r,ncfg", [("f32", 4, 7), ("f32", 8, 7), ("f64", 4, 3)])
+@pytest.mark.parametrize("dtype,r,ncfg", [("f32", 4, 7), ("f32", 8, 4), ("f64", 4, 3)])
 def test_tile_shapes_bitwise(oracle_mod, dtype, r, ncfg):
     # the per-point arithmetic does not depend on the tile shape or z chunk: any
     # difference would expose a race or an indexing error
