@@ -169,11 +169,112 @@ def run_cpu_baseline(budget_s: float = 12.0):
 
 
 def run_gradient():
-    raise NotImplementedError("gradient workload not built yet")
+    """The velocity-gradient workload: 256^3, r = 4, FP32, 2000 steps, true model = layers +
+    3 Gaussian anomalies, start model = layers, 128 x 128 surface receivers, L2 misfit,
+    checkpoints every 50 steps.  Times one FP32 gradient (forward with checkpoints, then
+    the checkpointed adjoint) after a warm-up; observed data from an FP32 forward in the
+    true model."""
+    import torch
+
+    import workloads
+    from paper_1410_1387_amd import Propagator
+    from paper_1410_1387_amd import fdwave as F
+    from paper_1410_1387_amd.autograd import GradientProblem, WaveProp, misfit
+
+    case = workloads.GradientCase()
+    v_true, v0 = case.models()
+    dt = case.courant * F.fd_dt_max(3, case.r, case.h, float(max(v_true.max(), v0.max())))
+    rec = case.receivers()
+    p = Propagator(torch.tensor(v_true, dtype=torch.float32, device="cuda"), case.r, case.h, dt, "f32",
+                   max_sources=1, max_receivers=len(rec))
+    p.inject(p.ricker(case.nsteps, case.f0), case.source)
+    obs = p.record(rec, case.nsteps)
+    p.step(case.nsteps)
+    p.sync()
+    obs = obs.clone()
+    p.close()
+    pb = GradientProblem(r=case.r, h=case.h, dt=dt, nsteps=case.nsteps, source=case.source, receivers=rec,
+                         f0=case.f0, ckpt=case.ckpt, dtype="f32")
+    v0t = torch.tensor(v0, dtype=torch.float32, device="cuda")
+
+    def once():
+        v = v0t.clone().requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tr = WaveProp.apply(v, pb)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        J = misfit(tr, obs)
+        J.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        return t1 - t0, t2 - t1, float(J), v.grad
+
+    once()
+    tf, tb, J, g = once()
+    n3 = case.n ** 3
+    finite = bool(torch.isfinite(g).all().item())
+    log(f"gradient: forward {tf:.3f} s, backward {tb:.3f} s, J {J:.4e}, finite={finite}")
+    return {
+        "workload": f"gradient_{case.n}_r{case.r}_fp32_{case.nsteps}steps_ckpt{case.ckpt}",
+        "gradient_s": round(tf + tb, 4), "forward_with_checkpoints_s": round(tf, 4), "backward_s": round(tb, 4),
+        "gpts_per_s": round(n3 * case.nsteps / (tf + tb) / 1e9, 2),
+        "unit": "grid points x time steps per second of a full gradient (forward + recompute + adjoint)",
+        "adjoint_step_us": round(tb / case.nsteps * 1e6, 1), "misfit": J, "finite": finite,
+        "receivers": len(rec), "checkpoints": (case.nsteps + case.ckpt - 1) // case.ckpt,
+    }
 
 
-def run_serving():
-    raise NotImplementedError("serving workload not built yet")
+def serving_requests(nreq=256):
+    """The serving trace: Poisson arrivals at 20 req/s, cubic sides uniform in
+    {128, 192, 256, 320, 400}, 500-2000 steps, r = 4, FP32, layered velocity per request
+    seed.  The layered model is expanded on the GPU from its depth profile."""
+    import torch
+
+    import workloads
+    from paper_1410_1387_amd import fdwave as F
+    from paper_1410_1387_amd.serving import ShotRequest
+
+    reqs = []
+    for q in workloads.serving_trace(nreq):
+        prof = q.profile().astype("float32")
+        dt = 0.5 * F.fd_dt_max(3, 4, 10.0, float(prof.max()))
+
+        def make(prof=prof, n=q.n):
+            col = torch.tensor(prof, device="cuda").view(n, 1, 1)
+            return col.expand(n, n, n).contiguous()
+
+        reqs.append(ShotRequest(rid=q.rid, velocity=make, shape=q.shape, nsteps=q.nsteps, source=q.source,
+                                receivers=q.receivers(), arrival=q.arrival, dt=dt))
+    return reqs
+
+
+def run_serving(nreq=256, budget_gib=96, sequential=True):
+    """Continuous batching of the serving trace, and the same trace served one shot at a
+    time, on the same GPU."""
+    from paper_1410_1387_amd.serving import ShotServer, run_sequential, summarize
+
+    reqs = serving_requests(nreq)
+    srv = ShotServer(r=4, dtype="f32", budget_bytes=budget_gib << 30, max_shots=64, chunk=32)
+    t0 = time.perf_counter()
+    res = srv.serve_trace(reqs)
+    wall = time.perf_counter() - t0
+    st = summarize(res)
+    st.update({"wall_s": round(wall, 2), "budget_gib": budget_gib, "chunk_steps": 32,
+               "max_resident_shots": srv.stats["max_resident_shots"],
+               "max_resident_gib": round(srv.stats["max_resident_bytes"] / 2 ** 30, 2),
+               "batched_chunks": srv.stats["chunks"]})
+    log(f"serving (continuous batching): {st['gpts_per_s']:.1f} Gpts/s, makespan {st['makespan_s']:.2f} s, "
+        f"p50 {st['p50_latency_s']:.2f} s, p99 {st['p99_latency_s']:.2f} s, max resident {st['max_resident_shots']}")
+    out = {"workload": f"serving_{nreq}req_poisson20_sides128-400_r4_fp32", "batched": st}
+    if sequential:
+        res1 = run_sequential(reqs)
+        s1 = summarize(res1)
+        log(f"serving (one at a time): {s1['gpts_per_s']:.1f} Gpts/s, makespan {s1['makespan_s']:.2f} s, "
+            f"p50 {s1['p50_latency_s']:.2f} s, p99 {s1['p99_latency_s']:.2f} s")
+        out["one_at_a_time"] = s1
+        out["throughput_ratio"] = round(st["gpts_per_s"] / s1["gpts_per_s"], 3) if s1["gpts_per_s"] else None
+    return out
 
 
 def main():

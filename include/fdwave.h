@@ -92,7 +92,7 @@ double fd_dt_max(int ndim, int r, double h, double vmax);
 /* ----------------------------------------------------------------- memory planning */
 
 /* Device bytes of one padded wavefield of this grid (the unit of checkpoints and of the
- * recompute ring used by the adjoint).  Layout: x-fastest rows with a 64-byte aligned
+ * recompute ring used by the adjoint).  Layout: x-fastest rows with a 128-byte aligned
  * interior, r zero ghost planes/rows on every face plus alignment padding; the padding
  * must stay zero.  *bytes written. */
 int fd_field_bytes(const fd_grid *g, int r, fd_dtype dtype, size_t *bytes);
@@ -191,6 +191,10 @@ int fd_step_explicit(fd_ctx *ctx, const void *cur, const void *prev, void *out, 
  *     mu^k = 2 mu^{k+1} - mu^{k+2} + c L^ mu^{k+1} + resid_amp sum_j c_j resid[k-1][j] e_j
  *     g   += mu^k * (L^ u^{k-1})
  * where L^ = h^2 L is the unscaled stencil.  dJ/dv = 2 g / v (fd_gradient_finish).
+ * The imaging sum is kept in the working precision.  With grad_seg given, it is blocked
+ * by segment: the segment's terms are summed into grad_seg and added to grad at the
+ * segment's last step, so rounding grows with segment length + segment count rather
+ * than with the step count.
  *   u_ckpt_cur, u_ckpt_prev  device padded u^{k_lo}, u^{k_lo - 1} (a forward checkpoint)
  *   ring      device, (k_hi - k_lo - 1) padded fields; filled with u^{k_lo+1} ..
  *             u^{k_hi-1} by recomputation from the checkpoint (may be NULL if
@@ -200,10 +204,13 @@ int fd_step_explicit(fd_ctx *ctx, const void *cur, const void *prev, void *out, 
  *   resid     device [T][nrec] of dtype, rows indexed by step n (receivers as given to
  *             fd_record)
  *   grad      device padded field of dtype, accumulated (zero it before the first segment)
- * Receivers must have been registered with fd_record (the traces buffer is not touched). */
+ *   grad_seg  device padded field of dtype used as the segment partial sum, or NULL for
+ *             plain accumulation into grad (its contents need no initialisation)
+ * Receivers must have been registered with fd_record (the traces buffer is not touched).
+ * resid must hold at least k_hi rows. */
 int fd_adjoint_segment(fd_ctx *ctx, const void *u_ckpt_cur, const void *u_ckpt_prev, int64_t k_lo,
                        int64_t k_hi, void *ring, void *mu, const void *resid, double resid_amp,
-                       void *grad);
+                       void *grad, void *grad_seg);
 
 /* dJ/dv = scale * 2 g / v on the dense grid.
  *   grad_padded  device padded accumulator from fd_adjoint_segment

@@ -190,7 +190,8 @@ struct fd_ctx {
     const FwdEntry *kf;
     const AdjEntry *ka;
     int zch;
-    int64_t tiles_x, tiles_y, chunks_z, adj_chunks_z;
+    int64_t tiles_x, tiles_y, chunks_z;
+    int64_t adj_tiles_x, adj_tiles_y, adj_chunks_z;
     int adj_zch;
     std::string cfg_name;
     // host mirrors
@@ -405,6 +406,10 @@ extern "C" int fd_create(fd_ctx **out, const fd_grid *g, int r, double h, double
     c->tiles_y = (L.kny + c->kf->by - 1) / c->kf->by;
     c->zch = tu.zchunk > 0 ? (int)std::min<int64_t>(tu.zchunk, L.knz) : choose_zch(c->tiles_x * c->tiles_y, L.knz, r);
     c->chunks_z = (L.knz + c->zch - 1) / c->zch;
+    c->adj_tiles_x = (L.knx + ka->bx - 1) / ka->bx;
+    c->adj_tiles_y = (L.kny + ka->by - 1) / ka->by;
+    c->adj_zch = choose_zch(c->adj_tiles_x * c->adj_tiles_y, L.knz, r);
+    c->adj_chunks_z = (L.knz + c->adj_zch - 1) / c->adj_zch;
     c->nrec = 0;
     c->traces = nullptr;
     c->rec_cap = 0;
@@ -672,7 +677,8 @@ extern "C" int fd_step_explicit(fd_ctx *ctx, const void *cur, const void *prev, 
 // ------------------------------------------------------------------ adjoint
 
 extern "C" int fd_adjoint_segment(fd_ctx *ctx, const void *u_ckpt_cur, const void *u_ckpt_prev, int64_t k_lo,
-                                  int64_t k_hi, void *ring, void *mu, const void *resid, double resid_amp, void *grad)
+                                  int64_t k_hi, void *ring, void *mu, const void *resid, double resid_amp, void *grad,
+                                  void *grad_seg)
 {
     int st = check_ctx(ctx);
     if (st) return st;
@@ -693,7 +699,7 @@ extern "C" int fd_adjoint_segment(fd_ctx *ctx, const void *u_ckpt_cur, const voi
     }
     // adjoint steps k = k_hi .. k_lo + 1
     void *m[2] = {mu, (char *)mu + fb};
-    const int64_t nwg = ctx->tiles_x * ctx->tiles_y * ctx->chunks_z;
+    const int64_t nwg = ctx->adj_tiles_x * ctx->adj_tiles_y * ctx->adj_chunks_z;
     for (int64_t k = k_hi; k > k_lo; --k) {
         AdjArgs a;
         std::memset(&a, 0, sizeof(a));
@@ -702,10 +708,19 @@ extern "C" int fd_adjoint_segment(fd_ctx *ctx, const void *u_ckpt_cur, const voi
         a.mu_out = m[k & 1];
         a.u_km1 = slot(k - 1 - k_lo);
         a.grad = grad;
+        a.gseg = grad_seg;
+        if (!grad_seg || nk == 1)
+            a.gmode = GM_DIRECT;
+        else
+            a.gmode = (k == k_hi) ? GM_FIRST : (k == k_lo + 1 ? GM_FOLD : GM_ACC);
         a.resid = resid;
         a.k = k;
         a.resid_amp = resid_amp;
         a.xcd_remap = ctx->xcd_remap;
+        a.zch = ctx->adj_zch;
+        a.tiles_x = (int32_t)ctx->adj_tiles_x;
+        a.tiles_y = (int32_t)ctx->adj_tiles_y;
+        a.chunks_z = (int32_t)ctx->adj_chunks_z;
         ctx->ka->launch(a, (int)nwg, ctx->stream);
         HIP_TRY(ctx, hipGetLastError());
     }

@@ -216,7 +216,7 @@ struct TileGeom {
     int hl[C::HPT];          // halo vector k: LDS offset
     bool hval[C::HPT];
 
-    __device__ __forceinline__ void init(const ShotDesc &s, int tx, int ty, int cz)
+    __device__ __forceinline__ void init(const ShotDesc &s, int tx, int ty, int cz, int zch)
     {
         const int tid = threadIdx.x;
         lx = (tid % C::TXN) * C::VEC;
@@ -225,8 +225,8 @@ struct TileGeom {
         y0 = ty * C::BY;
         gx = x0 + lx;
         gy = y0 + ly;
-        z0 = cz * s.zch;
-        z1 = min(z0 + s.zch, s.nz);
+        z0 = cz * zch;
+        z1 = min(z0 + zch, s.nz);
         col = s.off0 + (int64_t)gy * s.px + gx;
 #pragma unroll
         for (int e = 0; e < C::EY; ++e) {
@@ -326,7 +326,7 @@ __device__ __forceinline__ void fwd_tile(const ShotDesc &s, const typename C::ty
     const int64_t pxy = s.pxy;
 
     TileGeom<C> g;
-    g.init(s, tx, ty, cz);
+    g.init(s, tx, ty, cz, s.zch);
     if (g.z0 >= g.z1) return;
 
     // in-plane byte offsets (plane index zp = z + R counts the R ghost planes)
@@ -578,14 +578,22 @@ __global__ __launch_bounds__(C::NT) void fwd_kernel(LaunchArgs a)
 // One step of the discrete adjoint in the variable mu = c * lambda, fused with the
 // imaging condition:
 //     mu^k = 2 mu^{k+1} - mu^{k+2} + c Lh mu^{k+1} + resid_amp c_j resid[k-1][j] e_j
-//     g   += mu^k * Lh u^{k-1}
+//     t    = mu^k * Lh u^{k-1}
 // Two register queues (mu^{k+1}, u^{k-1}) march in z together; both planes are
-// staged in LDS.
+// staged in LDS.  The imaging term t is summed in the working precision, blocked by
+// checkpoint segment so that the rounding error grows with the segment length plus
+// the number of segments instead of with the number of steps:
+//     gmode 0: gseg += t         (inside a segment)
+//     gmode 1: gseg  = t         (first step of a segment)
+//     gmode 2: g    += gseg + t  (last step of a segment)
+//     gmode 3: g    += t         (unblocked)
+enum { GM_ACC = 0, GM_FIRST = 1, GM_FOLD = 2, GM_DIRECT = 3 };
 template <class C>
 __device__ __forceinline__ void adj_tile(const ShotDesc &s, const typename C::type *__restrict__ mcur,
                                          typename C::type *mout, const typename C::type *__restrict__ ucur,
-                                         typename C::type *grad, const typename C::type *__restrict__ resid,
-                                         int64_t k, typename C::type ramp, int tx, int ty, int cz,
+                                         typename C::type *grad, typename C::type *gseg, int gmode,
+                                         const typename C::type *__restrict__ resid,
+                                         int64_t k, typename C::type ramp, int tx, int ty, int cz, int zch,
                                          typename C::type *lds)
 {
     typedef typename C::type T;
@@ -595,8 +603,13 @@ __device__ __forceinline__ void adj_tile(const ShotDesc &s, const typename C::ty
     const int64_t px = s.px, pxy = s.pxy;
 
     TileGeom<C> g;
-    g.init(s, tx, ty, cz);
+    g.init(s, tx, ty, cz, zch);
     if (g.z0 >= g.z1) return;
+
+    // imaging accumulator: g1 (added through the FMA), g2 (added after it), gout (stored)
+    const T *g1 = gmode == GM_ACC ? gseg : (gmode == GM_FOLD ? gseg : (gmode == GM_DIRECT ? grad : nullptr));
+    const T *g2 = gmode == GM_FOLD ? grad : nullptr;
+    T *gout = (gmode == GM_ACC || gmode == GM_FIRST) ? gseg : grad;
 
     T qm[2 * R + 1][EY][VEC], qu[2 * R + 1][EY][VEC];
 #pragma unroll
@@ -611,7 +624,8 @@ __device__ __forceinline__ void adj_tile(const ShotDesc &s, const typename C::ty
                 vzero(qu[j][e]);
             }
         }
-    T nm[EY][VEC], nuu[EY][VEC], npv[EY][VEC], ncc[EY][VEC], ngr[EY][VEC], nhm[HPT][VEC], nhu[HPT][VEC];
+    T nm[EY][VEC], nuu[EY][VEC], npv[EY][VEC], ncc[EY][VEC], ngr[EY][VEC], ng2[EY][VEC], nhm[HPT][VEC],
+        nhu[HPT][VEC];
     {
         const int64_t zo = (int64_t)g.z0 * pxy;
 #pragma unroll
@@ -623,14 +637,16 @@ __device__ __forceinline__ void adj_tile(const ShotDesc &s, const typename C::ty
                 vzero(nm[e]);
                 vzero(nuu[e]);
             }
+            vzero(ngr[e]);
+            vzero(ng2[e]);
             if (g.rin[e]) {
                 vld_nt(npv[e], mout + g.col + e * px + zo);
                 vld_nt(ncc[e], cc + g.col + e * px + zo);
-                vld_nt(ngr[e], grad + g.col + e * px + zo);
+                if (g1) vld_nt(ngr[e], g1 + g.col + e * px + zo);
+                if (g2) vld_nt(ng2[e], g2 + g.col + e * px + zo);
             } else {
                 vzero(npv[e]);
                 vzero(ncc[e]);
-                vzero(ngr[e]);
             }
         }
 #pragma unroll
@@ -648,7 +664,7 @@ __device__ __forceinline__ void adj_tile(const ShotDesc &s, const typename C::ty
 
     int buf = 0;
     for (int z = g.z0; z < g.z1; ++z) {
-        T pv[EY][VEC], cv[EY][VEC], gv[EY][VEC], hm[HPT][VEC], hu[HPT][VEC];
+        T pv[EY][VEC], cv[EY][VEC], gv[EY][VEC], gv2[EY][VEC], hm[HPT][VEC], hu[HPT][VEC];
 #pragma unroll
         for (int e = 0; e < EY; ++e)
 #pragma unroll
@@ -658,6 +674,7 @@ __device__ __forceinline__ void adj_tile(const ShotDesc &s, const typename C::ty
                 pv[e][v] = npv[e][v];
                 cv[e][v] = ncc[e][v];
                 gv[e][v] = ngr[e][v];
+                gv2[e][v] = ng2[e][v];
             }
 #pragma unroll
         for (int j = 0; j < HPT; ++j)
@@ -677,7 +694,8 @@ __device__ __forceinline__ void adj_tile(const ShotDesc &s, const typename C::ty
                 if (g.rin[e]) {
                     vld_nt(npv[e], mout + g.col + e * px + zo);
                     vld_nt(ncc[e], cc + g.col + e * px + zo);
-                    vld_nt(ngr[e], grad + g.col + e * px + zo);
+                    if (g1) vld_nt(ngr[e], g1 + g.col + e * px + zo);
+                    if (g2) vld_nt(ng2[e], g2 + g.col + e * px + zo);
                 }
             }
 #pragma unroll
@@ -782,10 +800,13 @@ __device__ __forceinline__ void adj_tile(const ShotDesc &s, const typename C::ty
         for (int e = 0; e < EY; ++e) {
             T gn[VEC];
 #pragma unroll
-            for (int v = 0; v < VEC; ++v) gn[v] = fma_t(mnew[e][v], lapu[e][v], gv[e][v]);
+            for (int v = 0; v < VEC; ++v) {
+                gn[v] = fma_t(mnew[e][v], lapu[e][v], gv[e][v]);
+                if (g2) gn[v] = gn[v] + gv2[e][v];
+            }
             if (g.rin[e]) {
                 T *pm = mout + g.col + e * px + (int64_t)z * pxy;
-                T *pg = grad + g.col + e * px + (int64_t)z * pxy;
+                T *pg = gout + g.col + e * px + (int64_t)z * pxy;
                 if (g.gx + VEC <= s.nx) {
                     vst_nt(pm, mnew[e]);
                     vst_nt(pg, gn);
@@ -821,14 +842,14 @@ __global__ __launch_bounds__(C::NT) void adj_kernel(AdjArgs a)
     int wg = blockIdx.x;
     if (a.xcd_remap) wg = xcd_remap(wg, (int)gridDim.x);
     const ShotDesc &s = *a.shot;
-    const int tx = wg % s.tiles_x;
-    const int t2 = wg / s.tiles_x;
-    const int ty = t2 % s.tiles_y;
-    const int cz = t2 / s.tiles_y;
-    if (cz >= s.chunks_z) return;
+    const int tx = wg % a.tiles_x;
+    const int t2 = wg / a.tiles_x;
+    const int ty = t2 % a.tiles_y;
+    const int cz = t2 / a.tiles_y;
+    if (cz >= a.chunks_z) return;
     adj_tile<C>(s, static_cast<const T *>(a.mu_cur), static_cast<T *>(a.mu_out),
-                static_cast<const T *>(a.u_km1), static_cast<T *>(a.grad),
-                static_cast<const T *>(a.resid), a.k, T(a.resid_amp), tx, ty, cz, lds);
+                static_cast<const T *>(a.u_km1), static_cast<T *>(a.grad), static_cast<T *>(a.gseg), a.gmode,
+                static_cast<const T *>(a.resid), a.k, T(a.resid_amp), tx, ty, cz, a.zch, lds);
 }
 
 // ------------------------------------------------------------------ registry

@@ -60,11 +60,15 @@ struct AdjArgs {
     void *mu_out;          // in: mu^{k+2}, out: mu^k
     const void *u_km1;     // u^{k-1}
     void *grad;            // accumulator g (padded)
+    void *gseg;            // segment partial sum of the imaging term (padded), or null
+    int32_t gmode;         // imaging accumulation, see adj_tile
+    int32_t pad1;
     const void *resid;     // [T][nrec]
     int64_t k;             // adjoint step index (residual row k - 1)
     double resid_amp;
     int32_t xcd_remap;
-    int32_t pad0;
+    int32_t zch;           // the adjoint kernel's own tiling (its tile differs from the forward one)
+    int32_t tiles_x, tiles_y, chunks_z, pad0;
 };
 
 }  // namespace fdw

@@ -79,7 +79,7 @@ def lib():
             "fd_get_state": (ctypes.c_int, [P, P, P, ctypes.POINTER(I64), ctypes.c_int]),
             "fd_set_state": (ctypes.c_int, [P, P, P, I64, ctypes.c_int]),
             "fd_step_explicit": (ctypes.c_int, [P, P, P, P, I64]),
-            "fd_adjoint_segment": (ctypes.c_int, [P, P, P, I64, I64, P, P, P, D, P]),
+            "fd_adjoint_segment": (ctypes.c_int, [P, P, P, I64, I64, P, P, P, D, P, P]),
             "fd_gradient_finish": (ctypes.c_int, [P, P, P, P, D]),
             "fd_batch_workspace_bytes": (SZ, [ctypes.c_int]),
             "fd_batch_create": (ctypes.c_int, [ctypes.POINTER(P), ctypes.c_int, P, SZ, P]),
@@ -242,9 +242,10 @@ def fd_step_explicit(ctx: int, cur, prev, out, step: int):
     _check(lib().fd_step_explicit(ctx, ptr(cur), ptr(prev), ptr(out), int(step)), "fd_step_explicit")
 
 
-def fd_adjoint_segment(ctx: int, ckpt_cur, ckpt_prev, k_lo: int, k_hi: int, ring, mu, resid, resid_amp: float, grad):
+def fd_adjoint_segment(ctx: int, ckpt_cur, ckpt_prev, k_lo: int, k_hi: int, ring, mu, resid, resid_amp: float, grad,
+                       grad_seg=None):
     _check(lib().fd_adjoint_segment(ctx, ptr(ckpt_cur), ptr(ckpt_prev), int(k_lo), int(k_hi), ptr(ring), ptr(mu),
-                                    ptr(resid), float(resid_amp), ptr(grad)), "fd_adjoint_segment")
+                                    ptr(resid), float(resid_amp), ptr(grad), ptr(grad_seg)), "fd_adjoint_segment")
 
 
 def fd_gradient_finish(ctx: int, grad_padded, velocity, out, scale: float):

@@ -1,0 +1,379 @@
+"""Continuous batching of forward shots on one GPU.
+
+``ShotServer`` runs a persistent request loop in a worker thread:
+
+* requests are submitted at any time (``submit`` returns a Future);
+* the loop admits queued requests in arrival order while their HBM footprint
+  (workspace + traces + wavelet) fits the budget and a batch slot is free; a shot's
+  context is created on a separate setup stream, so admission overlaps with the
+  batched work already on the GPU;
+* all admitted shots -- different grid sizes, same radius and dtype -- advance
+  together in one stencil launch per time step (``fd_batch_step``): every workgroup
+  finds its (shot, tile) in a prefix table and every shot keeps its step counter in
+  device memory, so a chunk of an even number of steps is a captured HIP graph that
+  is replayed while shots come and go;
+* after each chunk the loop retires shots whose counters reached their step count,
+  frees their memory and admits new ones at the next chunk boundary.
+
+Each shot's wavefields stay resident in HBM from admission to completion.  Results
+are the receiver traces; latency is completion minus arrival.  ``run_sequential``
+serves the same requests one at a time (one shot on the GPU at once) for comparison.
+"""
+
+from __future__ import annotations
+
+import collections
+import concurrent.futures as cf
+import dataclasses
+import math
+import queue
+import threading
+import time
+from typing import Any, Callable, Optional
+
+import numpy as np
+import torch
+
+from . import fdwave as F
+
+
+@dataclasses.dataclass
+class ShotRequest:
+    """One shot: velocity (dense (nz, ny, nx) array, or a callable returning one), step count,
+    Ricker source (f0, shift t0 = 1.5/f0 by default) at ``source`` (x, y, z), receivers
+    [nrec, 3].  ``arrival`` (s, relative to the start of a trace) is used by ``serve_trace``."""
+
+    rid: int
+    velocity: Any
+    nsteps: int
+    source: tuple
+    receivers: np.ndarray
+    h: float = 10.0
+    courant: float = 0.5
+    f0: float = 15.0
+    t0: Optional[float] = None
+    arrival: float = 0.0
+    dt: Optional[float] = None   # explicit time step; default courant * fd_dt_max(max v)
+    shape: Optional[tuple] = None  # grid shape; required when velocity is a callable
+
+    def grid_shape(self) -> tuple:
+        if self.shape is not None:
+            return tuple(self.shape)
+        if callable(self.velocity):
+            raise ValueError("shape is required when velocity is a callable")
+        return tuple(np.shape(self.velocity))
+
+
+@dataclasses.dataclass
+class ShotResult:
+    rid: int
+    status: str                      # "ok" or "failed"
+    traces: Optional[torch.Tensor]   # [nsteps, nrec] on the GPU
+    arrival: float
+    admitted: float
+    completed: float
+    points: int                      # grid points x steps
+    error: str = ""
+
+    @property
+    def latency(self) -> float:
+        return self.completed - self.arrival
+
+
+class _Live:
+    """A shot resident on the GPU."""
+
+    def __init__(self, req: ShotRequest, ctx: int, tensors: list, traces: torch.Tensor, footprint: int,
+                 npoints: int, arrival: float, admitted: float, future: cf.Future):
+        self.req, self.ctx, self.tensors, self.traces = req, ctx, tensors, traces
+        self.footprint, self.npoints = footprint, npoints
+        self.arrival, self.admitted, self.future = arrival, admitted, future
+
+
+def shot_footprint(shape, nsteps: int, nrec: int, r: int, dtype: str) -> int:
+    """HBM bytes a shot holds while resident: context workspace (2 wavefields, c, tables),
+    traces and wavelet."""
+    es = 4 if dtype == "f32" else 8
+    return F.fd_workspace_bytes(shape, r, dtype, 1, nrec) + (nsteps * nrec + nsteps) * es
+
+
+class _ShotFactory:
+    """Creates one shot's context and device buffers on a given stream."""
+
+    def __init__(self, r: int, dtype: str, device):
+        self.r, self.dtype, self.device = r, dtype, device
+        self.tdt = torch.float32 if dtype == "f32" else torch.float64
+        self.npdt = np.float32 if dtype == "f32" else np.float64
+
+    def create(self, req: ShotRequest, stream: torch.cuda.Stream):
+        nrec = len(req.receivers)
+        sp = F.stream_ptr(stream)
+        with torch.cuda.stream(stream):
+            vin = req.velocity() if callable(req.velocity) else req.velocity
+            if isinstance(vin, torch.Tensor):  # already a device tensor (e.g. built on the GPU)
+                v = vin.to(device=self.device, dtype=self.tdt).contiguous()
+            else:
+                v = torch.from_numpy(np.ascontiguousarray(vin, dtype=self.npdt)).to(self.device)
+            shape = tuple(v.shape)
+            ws = torch.empty(F.fd_workspace_bytes(shape, self.r, self.dtype, 1, nrec), dtype=torch.uint8,
+                             device=self.device)
+            wav = torch.empty(req.nsteps, dtype=self.tdt, device=self.device)
+            traces = torch.zeros((req.nsteps, nrec), dtype=self.tdt, device=self.device)
+        dt = req.dt if req.dt is not None else req.courant * F.fd_dt_max(len(shape), self.r, req.h,
+                                                                             float(v.max()))
+        ctx = F.fd_create(shape, self.r, req.h, dt, v, self.dtype, "zero", ws, 1, nrec, sp)
+        try:
+            F.fd_ricker(wav, dt, req.f0, 1.5 / req.f0 if req.t0 is None else req.t0, sp)
+            F.fd_inject(ctx, wav, req.source, 1.0)
+            F.fd_record(ctx, req.receivers, traces, req.nsteps)
+            F.fd_sync(ctx)
+        except Exception:
+            F.fd_destroy(ctx)
+            raise
+        del v
+        footprint = ws.numel() + (wav.numel() + traces.numel()) * traces.element_size()
+        return ctx, [ws, wav], traces, footprint, int(np.prod(shape)) * req.nsteps
+
+
+class ShotServer:
+    """Persistent continuous-batching server for same-radius, same-dtype shots.
+
+    budget_bytes  HBM the resident shots may hold together
+    max_shots     batch slots (shots advanced by one launch)
+    chunk         time steps per batched launch sequence (even: replayed as a graph)
+    """
+
+    def __init__(self, r: int = 4, dtype: str = "f32", budget_bytes: int = 64 << 30, max_shots: int = 64,
+                 chunk: int = 32, device: str = "cuda"):
+        self.r, self.dtype = r, dtype
+        self.budget, self.max_shots, self.chunk = int(budget_bytes), int(max_shots), int(chunk)
+        self.device = torch.device(device)
+        if self.device.index is None:  # the worker thread needs an explicit device index
+            self.device = torch.device(self.device.type, torch.cuda.current_device())
+        self._factory = _ShotFactory(r, dtype, self.device)
+        self._outstanding: set = set()   # futures the loop has taken from the inbox
+        self._inbox: "queue.Queue" = queue.Queue()
+        self._thread: Optional[threading.Thread] = None
+        self._stop = threading.Event()
+        self.t0 = time.perf_counter()
+        self.stats = {"chunks": 0, "membership_changes": 0, "max_resident_bytes": 0, "max_resident_shots": 0,
+                      "gpu_points": 0}
+        self._error: Optional[BaseException] = None
+
+    # ------------------------------------------------------------------ public API
+
+    def now(self) -> float:
+        return time.perf_counter() - self.t0
+
+    def start(self):
+        if self._thread is None:
+            self.t0 = time.perf_counter()
+            self._thread = threading.Thread(target=self._loop_guarded, name="shot-server", daemon=True)
+            self._thread.start()
+        return self
+
+    def submit(self, req: ShotRequest, arrival: Optional[float] = None) -> cf.Future:
+        fut: cf.Future = cf.Future()
+        self._inbox.put((req, self.now() if arrival is None else arrival, fut))
+        return fut
+
+    def stop(self):
+        self._stop.set()
+        if self._thread is not None:
+            self._thread.join()
+            self._thread = None
+        if self._error is not None:
+            raise self._error
+
+    def serve_trace(self, requests: list, realtime: bool = True) -> list:
+        """Submit each request at its arrival time (seconds after start) and wait for all."""
+        self.start()
+        futs = []
+        for req in sorted(requests, key=lambda q: q.arrival):
+            if realtime:
+                delay = req.arrival - self.now()
+                if delay > 0:
+                    time.sleep(delay)
+            futs.append(self.submit(req, req.arrival if realtime else self.now()))
+        for f in futs:
+            while not f.done():
+                if self._thread is None or not self._thread.is_alive():
+                    break
+                try:
+                    f.result(timeout=0.5)
+                except cf.TimeoutError:
+                    pass
+        self.stop()  # raises the worker's exception, if it died
+        return [f.result() for f in futs]
+
+    # ------------------------------------------------------------------ the loop
+
+    def _loop_guarded(self):
+        try:
+            self._loop()
+        except BaseException as e:  # surface to stop(); fail every waiting future
+            self._error = e
+            for fut in list(self._outstanding):
+                if not fut.done():
+                    fut.set_exception(e)
+            while True:
+                try:
+                    _, _, fut = self._inbox.get_nowait()
+                except queue.Empty:
+                    break
+                if not fut.done():
+                    fut.set_exception(e)
+
+    def _fail(self, req, arrival, fut, err: str):
+        now = self.now()
+        fut.set_result(ShotResult(req.rid, "failed", None, arrival, now, now, 0, err))
+        self._outstanding.discard(fut)
+
+    def _loop(self):
+        torch.cuda.set_device(self.device)
+        bstream = torch.cuda.Stream(device=self.device)   # batched chunks
+        sstream = torch.cuda.Stream(device=self.device)   # shot setup
+        bws = torch.empty(F.fd_batch_workspace_bytes(self.max_shots), dtype=torch.uint8, device=self.device)
+        batch = F.fd_batch_create(self.max_shots, bws, F.stream_ptr(bstream))
+        pending: collections.deque = collections.deque()
+        active: list = []
+        used = 0
+        dirty = False
+        inflight: collections.deque = collections.deque()   # (event, [shots finishing in that chunk])
+        try:
+            while True:
+                # drain the inbox; block only when there is nothing else to do
+                block = not active and not pending
+                while True:
+                    try:
+                        item = self._inbox.get(timeout=0.005) if block else self._inbox.get_nowait()
+                    except queue.Empty:
+                        break
+                    pending.append(item)
+                    self._outstanding.add(item[2])
+                    block = False
+                if not active and not pending and not inflight:
+                    if self._stop.is_set():
+                        break
+                    continue
+                # admit in arrival order while the head fits
+                while pending and len(active) < self.max_shots:
+                    req, arrival, fut = pending[0]
+                    try:
+                        need = shot_footprint(req.grid_shape(), req.nsteps, len(req.receivers), self.r, self.dtype)
+                    except Exception as e:  # malformed request
+                        pending.popleft()
+                        self._fail(req, arrival, fut, f"bad request: {e}")
+                        continue
+                    if need > self.budget:
+                        pending.popleft()
+                        self._fail(req, arrival, fut, f"footprint {need} B exceeds the budget {self.budget} B")
+                        continue
+                    if used + need > self.budget:
+                        break  # wait for memory: head-of-line order is kept
+                    pending.popleft()
+                    try:
+                        ctx, tensors, traces, fp, npts = self._factory.create(req, sstream)
+                    except F.FdError as e:
+                        self._fail(req, arrival, fut, str(e))
+                        continue
+                    for t in tensors + [traces]:  # written by batched kernels on bstream
+                        t.record_stream(bstream)
+                    active.append(_Live(req, ctx, tensors, traces, fp, npts, arrival, self.now(), fut))
+                    used += fp
+                    dirty = True
+                self.stats["max_resident_bytes"] = max(self.stats["max_resident_bytes"], used)
+                self.stats["max_resident_shots"] = max(self.stats["max_resident_shots"], len(active))
+                if not active and not inflight:
+                    continue
+                if dirty:
+                    # fd_batch_set waits for the in-flight chunks before rewriting the table
+                    self._retire_done(inflight, wait_all=True)
+                    keep = [s for s in active if not s.future.done()]
+                    for s in active:
+                        if s.future.done():
+                            used -= s.footprint
+                            F.fd_destroy(s.ctx)
+                            s.tensors = None
+                    active = keep
+                    F.fd_batch_set(batch, [s.ctx for s in active], [s.req.nsteps for s in active])
+                    self.stats["membership_changes"] += 1
+                    dirty = False
+                    if not active:
+                        continue
+                F.fd_batch_step(batch, self.chunk)
+                ev = torch.cuda.Event()
+                ev.record(bstream)
+                finishing = [s for s in active if F.fd_get_step(s.ctx) >= s.req.nsteps and not s.future.done()
+                             and not getattr(s, "_queued_done", False)]
+                for s in finishing:
+                    s._queued_done = True
+                    self.stats["gpu_points"] += s.npoints
+                inflight.append((ev, finishing))
+                self.stats["chunks"] += 1
+                if len(inflight) > 1:
+                    if self._retire_done(inflight, wait_all=False):
+                        dirty = True
+        finally:
+            self._retire_done(inflight, wait_all=True)
+            for s in active:
+                if not s.future.done():
+                    s.future.set_exception(RuntimeError("server stopped"))
+                F.fd_destroy(s.ctx)
+            F.fd_batch_destroy(batch)
+
+    def _retire_done(self, inflight, wait_all: bool) -> bool:
+        """Complete the shots of finished chunks (all in-flight chunks when wait_all, else all
+        but the newest).  Returns True if any shot completed."""
+        any_done = False
+        while inflight and (wait_all or len(inflight) > 1):
+            ev, finishing = inflight.popleft()
+            ev.synchronize()
+            now = self.now()
+            for s in finishing:
+                s.future.set_result(ShotResult(s.req.rid, "ok", s.traces, s.arrival, s.admitted, now, s.npoints))
+                self._outstanding.discard(s.future)
+                any_done = True
+        return any_done
+
+
+def run_sequential(requests: list, r: int = 4, dtype: str = "f32", realtime: bool = True,
+                   device: str = "cuda") -> list:
+    """Serve the requests one at a time in arrival order (one shot on the GPU at once,
+    fd_step with one launch per step): the baseline the batched server is compared with."""
+    dev = torch.device(device)
+    factory = _ShotFactory(r, dtype, dev)
+    stream = torch.cuda.Stream(device=dev)
+    t0 = time.perf_counter()
+    now = lambda: time.perf_counter() - t0  # noqa: E731
+    out = []
+    for req in sorted(requests, key=lambda q: q.arrival):
+        if realtime and req.arrival > now():
+            time.sleep(req.arrival - now())
+        arrival = req.arrival if realtime else now()
+        start = now()
+        try:
+            ctx, tensors, traces, fp, npts = factory.create(req, stream)
+        except F.FdError as e:
+            out.append(ShotResult(req.rid, "failed", None, arrival, start, now(), 0, str(e)))
+            continue
+        F.fd_set_stream(ctx, F.stream_ptr(stream))
+        F.fd_step(ctx, req.nsteps)
+        F.fd_sync(ctx)
+        out.append(ShotResult(req.rid, "ok", traces, arrival, start, now(), npts))
+        F.fd_destroy(ctx)
+    return out
+
+
+def summarize(results: list, makespan: Optional[float] = None) -> dict:
+    ok = [r for r in results if r.status == "ok"]
+    lat = np.array([r.latency for r in ok]) if ok else np.zeros(1)
+    pts = sum(r.points for r in ok)
+    if makespan is None:
+        makespan = max(r.completed for r in ok) - min(r.arrival for r in ok) if ok else 0.0
+    return {
+        "requests": len(results), "completed": len(ok), "failed": len(results) - len(ok),
+        "makespan_s": makespan, "gpts_per_s": pts / makespan / 1e9 if makespan > 0 else 0.0,
+        "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
+        "mean_latency_s": float(lat.mean()), "point_updates": pts,
+    }

@@ -1,0 +1,158 @@
+"""Batched (graph-replayed) stepping and the continuous-batching shot server (needs an
+MI355X).  A shot must give bitwise the same traces and wavefield alone and in any mix,
+because the per-point arithmetic of the batched kernel is that of the single-shot one."""
+
+import numpy as np
+import pytest
+
+import workloads
+from gpu_util import rel_l2, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _shot(shape, nsteps, seed):
+    v = workloads.layered_velocity(shape, seed=seed).astype(np.float32)
+    nz, ny, nx = shape
+    src = (nx // 2, ny // 2, 2)
+    rec = workloads.surface_receivers(nx, ny, 2, 3)
+    return v, src, rec, nsteps
+
+
+def _make_ctx(v, src, rec, T, dt, stream):
+    import torch
+
+    from paper_1410_1387_amd import fdwave as F
+
+    vt = torch.tensor(v, device="cuda")
+    ws = torch.empty(F.fd_workspace_bytes(v.shape, 4, "f32", 1, len(rec)), dtype=torch.uint8, device="cuda")
+    wav = torch.empty(T, dtype=torch.float32, device="cuda")
+    tr = torch.zeros((T, len(rec)), dtype=torch.float32, device="cuda")
+    sp = F.stream_ptr(stream)
+    ctx = F.fd_create(v.shape, 4, 10.0, dt, vt, "f32", "zero", ws, 1, len(rec), sp)
+    F.fd_ricker(wav, dt, 30.0, 0.03, sp)
+    F.fd_inject(ctx, wav, src, 1.0)
+    F.fd_record(ctx, rec, tr, T)
+    return ctx, [vt, ws, wav], tr
+
+
+def test_batched_graph_replays_match_single(oracle_mod):
+    import torch
+
+    from paper_1410_1387_amd import fdwave as F
+
+    shots = [_shot((20, 24, 28), 30, 1), _shot((33, 40, 37), 47, 2), _shot((16, 16, 70), 21, 3)]
+    dt = 0.45 * min(oracle_mod.dt_max(3, 4, 10.0, float(s[0].max())) for s in shots)
+    stream = torch.cuda.Stream()
+    chunk = 8
+    # eager reference: each shot alone, state saved at every chunk boundary
+    refs = []
+    for (v, src, rec, T) in shots:
+        ctx, keep, tr = _make_ctx(v, src, rec, T, dt, stream)
+        states = []
+        done = 0
+        while done < T:
+            n = min(chunk, T - done)
+            F.fd_step(ctx, n)
+            done += n
+            u = torch.empty(v.shape, dtype=torch.float32, device="cuda")
+            F.fd_get_state(ctx, u, None)
+            F.fd_sync(ctx)
+            states.append(u.cpu().numpy())
+        refs.append((states, tr.cpu().numpy()))
+        F.fd_destroy(ctx)
+    # batched: one launch per step for all three shots, graph-captured chunks
+    ctxs = [_make_ctx(v, src, rec, T, dt, stream) for (v, src, rec, T) in shots]
+    bws = torch.empty(F.fd_batch_workspace_bytes(4), dtype=torch.uint8, device="cuda")
+    b = F.fd_batch_create(4, bws, F.stream_ptr(stream))
+    F.fd_batch_set(b, [c[0] for c in ctxs], [s[3] for s in shots])
+    for i in range(max(len(r[0]) for r in refs)):
+        say(f"batched chunk {i}")
+        F.fd_batch_step(b, chunk)
+        stream.synchronize()
+        for j, (ctx, keep, tr) in enumerate(ctxs):
+            states = refs[j][0]
+            k = min(i, len(states) - 1)
+            u = torch.empty(shots[j][0].shape, dtype=torch.float32, device="cuda")
+            F.fd_get_state(ctx, u, None)
+            F.fd_sync(ctx)
+            assert F.fd_get_step(ctx) == min((i + 1) * chunk, shots[j][3])
+            assert np.array_equal(u.cpu().numpy(), states[k]), (i, j)
+    for j, (ctx, keep, tr) in enumerate(ctxs):
+        assert np.array_equal(tr.cpu().numpy(), refs[j][1])
+        F.fd_destroy(ctx)
+    F.fd_batch_destroy(b)
+    # and the batched result is the oracle's
+    v, src, rec, T = shots[1]
+    ref = oracle_mod.forward(v.astype(np.float64), 10.0, dt, 4, T, [(src, oracle_mod.ricker(T, dt, 30.0, 0.03))], rec)
+    assert rel_l2(refs[1][1], ref["traces"]) <= 1e-4
+
+
+def _requests(n, seed, sides=(24, 32, 40), steps=(40, 90), spread=0.3):
+    from paper_1410_1387_amd.serving import ShotRequest
+
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        s = int(rng.choice(sides))
+        v, src, rec, T = _shot((s, s, s), int(rng.integers(steps[0], steps[1] + 1)), seed * 100 + i)
+        out.append(ShotRequest(rid=i, velocity=v, nsteps=T, source=src, receivers=rec, f0=30.0, t0=0.03,
+                               arrival=float(rng.uniform(0, spread)), dt=4e-4))
+    return out
+
+
+def test_server_alone_vs_mix_bitwise(oracle_mod):
+    from paper_1410_1387_amd.serving import ShotServer, run_sequential, summarize
+
+    reqs = _requests(10, 5, steps=(300, 600), spread=0.02)  # arrivals overlap running shots
+    say("sequential baseline")
+    seq = {r.rid: r for r in run_sequential(reqs)}
+    say("continuous batching")
+    srv = ShotServer(r=4, chunk=8, max_shots=8)
+    res = {r.rid: r for r in srv.serve_trace(reqs)}
+    st = summarize(list(res.values()))
+    say(f"served {st['completed']} p50 {st['p50_latency_s']:.3f}s p99 {st['p99_latency_s']:.3f}s; {srv.stats}")
+    assert st["completed"] == len(reqs)
+    assert srv.stats["max_resident_shots"] > 1  # shots really shared launches
+    for rid, r in res.items():
+        assert r.status == "ok" and seq[rid].status == "ok"
+        assert np.array_equal(r.traces.cpu().numpy(), seq[rid].traces.cpu().numpy()), rid
+    q = reqs[3]
+    ref = oracle_mod.forward(q.velocity.astype(np.float64), q.h, q.dt, 4, q.nsteps,
+                             [(q.source, oracle_mod.ricker(q.nsteps, q.dt, q.f0, q.t0))], q.receivers)
+    assert rel_l2(res[3].traces.cpu().numpy(), ref["traces"]) <= 1e-4
+
+
+def test_server_budget_backpressure():
+    from paper_1410_1387_amd.serving import ShotServer, run_sequential, shot_footprint
+
+    reqs = _requests(6, 6, sides=(32, 40), spread=0.0)
+    need = max(shot_footprint(q.velocity.shape, q.nsteps, len(q.receivers), 4, "f32") for q in reqs)
+    budget = int(need * 1.6)  # room for one shot at a time, sometimes two
+    say(f"budget {budget} B")
+    srv = ShotServer(r=4, chunk=8, max_shots=8, budget_bytes=budget)
+    res = {r.rid: r for r in srv.serve_trace(reqs, realtime=False)}
+    seq = {r.rid: r for r in run_sequential(reqs, realtime=False)}
+    assert all(r.status == "ok" for r in res.values())
+    assert srv.stats["max_resident_bytes"] <= budget
+    for rid in res:
+        assert np.array_equal(res[rid].traces.cpu().numpy(), seq[rid].traces.cpu().numpy())
+
+
+def test_server_isolates_bad_requests():
+    from paper_1410_1387_amd.serving import ShotServer, ShotRequest
+
+    reqs = _requests(4, 7, spread=0.0)
+    v = reqs[0].velocity
+    reqs.append(ShotRequest(rid=90, velocity=v, nsteps=20, source=(1, 1, 1), receivers=reqs[0].receivers,
+                            dt=1.0))                                   # unstable time step
+    reqs.append(ShotRequest(rid=91, velocity=v, nsteps=20, source=(999, 1, 1), receivers=reqs[0].receivers,
+                            dt=4e-4))                                  # source outside the grid
+    big = np.full((400, 400, 400), 2000.0, dtype=np.float32)
+    reqs.append(ShotRequest(rid=92, velocity=big, nsteps=10, source=(1, 1, 1), receivers=reqs[0].receivers))
+    srv = ShotServer(r=4, chunk=8, max_shots=8, budget_bytes=1 << 30)  # 400^3 does not fit 1 GiB
+    res = {r.rid: r for r in srv.serve_trace(reqs, realtime=False)}
+    assert res[90].status == "failed" and "UNSTABLE" in res[90].error
+    assert res[91].status == "failed" and "RANGE" in res[91].error
+    assert res[92].status == "failed" and "budget" in res[92].error
+    assert all(res[i].status == "ok" for i in range(4))

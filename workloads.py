@@ -23,15 +23,22 @@ import numpy as np
 # ----------------------------------------------------------------------------- velocity models
 
 
+def layered_profile(nd: int, nlayers: int = 8, vmin: float = 1500.0, vmax: float = 4500.0,
+                    seed: int = 0) -> np.ndarray:
+    """Velocity per depth index of ``nlayers`` horizontal layers of equal thickness, drawn
+    top to bottom from U[vmin, vmax] (unsorted)."""
+    rng = np.random.default_rng(seed)
+    vel = rng.uniform(vmin, vmax, size=nlayers)
+    layer = np.minimum((np.arange(nd) * nlayers) // nd, nlayers - 1)
+    return vel[layer]
+
+
 def layered_velocity(shape, nlayers: int = 8, vmin: float = 1500.0, vmax: float = 4500.0,
                      seed: int = 0, dtype=np.float64) -> np.ndarray:
     """Horizontal layers of equal thickness along the slowest (depth) axis, velocities
     drawn top to bottom from U[vmin, vmax] (unsorted).  shape is (nz, ny, nx) or (ny, nx)."""
-    rng = np.random.default_rng(seed)
-    vel = rng.uniform(vmin, vmax, size=nlayers)
     nd = shape[0]
-    layer = np.minimum((np.arange(nd) * nlayers) // nd, nlayers - 1)
-    prof = vel[layer]
+    prof = layered_profile(nd, nlayers, vmin, vmax, seed)
     v = np.broadcast_to(prof.reshape((nd,) + (1,) * (len(shape) - 1)), shape)
     return np.ascontiguousarray(v, dtype=dtype)
 
@@ -224,6 +231,10 @@ class ServeRequest:
 
     def velocity(self, dtype=np.float32):
         return layered_velocity(self.shape, seed=self.seed, dtype=dtype)
+
+    def profile(self) -> np.ndarray:
+        """Velocity per depth index of this request's layered model."""
+        return layered_profile(self.n, seed=self.seed)
 
     @property
     def points(self) -> int:
