@@ -10,7 +10,8 @@ A shot runs every row of the forward path on the GPU: model preparation
 stencil launches with the source and receivers fused in.  The velocity model is
 resident in HBM before the timed region starts.
 
-    python bench.py [--steps K] [--warmup W] [--no-cpu] [--gradient] [--serving]
+    python bench.py [--steps K] [--warmup W] [--no-cpu] [--gradient] [--serving] [--copy-probe]
+    python bench.py --summarize-prof DIR     # rocprofv3 CSVs -> profiles/ summary
 
 Prints one JSON line.
 """
@@ -127,10 +128,76 @@ def run_forward(args):
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": None if tr is None else round(tr / (launch_ms * 1e-3) / 1e9, 1),
+            "traffic_bytes_per_launch": tr,
             "algorithmic_bytes_per_launch": algo_bytes, "launch_us": round(launch_ms * 1e3, 2),
             "stencil_gpts_per_s": round(pts / (launch_ms * 1e-3) / 1e9, 2),
         },
     }
+
+
+def run_copy_probe(nbytes=1 << 30, reps=3):
+    """A plain device copy of known size: the reference that hardware byte counters are
+    scaled by (what FETCH_SIZE / WRITE_SIZE report for exactly nbytes read and written)."""
+    import torch
+
+    from paper_1410_1387_amd import fdwave as F
+
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        F.fd_copy_probe(b, a, nbytes, F.stream_ptr())
+    torch.cuda.synchronize()
+    del a, b
+
+
+def summarize_prof(d: str, out_json: str = PROFILE_TRAFFIC):
+    """Reduce a rocprofv3 directory (trace/, fetch/, write/ subdirectories of CSV output) to
+    per-launch HBM bytes of the forward stencil kernel, scaled by the copy-probe factors."""
+    import csv
+    import glob
+
+    def rows(pattern):
+        out = []
+        for f in glob.glob(os.path.join(d, pattern)):
+            with open(f) as fh:
+                out += list(csv.DictReader(fh))
+        return out
+
+    def counter(pattern, name):
+        vals = {}
+        for r in rows(pattern):
+            if r["Counter_Name"] == name:
+                vals.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        return {k: sum(v) / len(v) for k, v in vals.items()}
+
+    fetch = counter("fetch/*counter_collection.csv", "FETCH_SIZE")
+    write = counter("write/*counter_collection.csv", "WRITE_SIZE")
+    copy = [k for k in fetch if "copy_probe" in k][0]
+    fwd = max((k for k in fetch if "fwd_kernel" in k), key=lambda k: fetch[k])
+    probe_bytes = 1 << 30
+    f_scale = probe_bytes / (fetch[copy] * 1024.0)
+    w_scale = probe_bytes / (write[copy] * 1024.0)
+    stats = {r["Name"]: r for r in rows("trace/*kernel_stats.csv")}
+    avg_ns = float(stats[fwd]["AverageNs"]) if fwd in stats else None
+    fb, wb = fetch[fwd] * 1024.0 * f_scale, write[fwd] * 1024.0 * w_scale
+    res = {
+        "kernel": fwd, "kernel_hash": kernel_hash(),
+        "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb, "hbm_bytes_per_launch": fb + wb,
+        "algorithmic_bytes_per_launch": 16.0 * 512 ** 3,
+        "fetch_scale": f_scale, "write_scale": w_scale, "copy_probe_bytes": probe_bytes,
+        "trace_avg_launch_ns": avg_ns,
+        "commands": [
+            "rocprofv3 --kernel-trace --stats -d DIR/trace -o trace --output-format csv -- "
+            "python3 bench.py --steps 1 --warmup 0 --no-cpu --copy-probe",
+            "rocprofv3 --pmc FETCH_SIZE -d DIR/fetch -o fetch --output-format csv -- "
+            "python3 bench.py --steps 1 --warmup 0 --no-cpu --copy-probe",
+            "rocprofv3 --pmc WRITE_SIZE -d DIR/write -o write --output-format csv -- "
+            "python3 bench.py --steps 1 --warmup 0 --no-cpu --copy-probe",
+        ],
+    }
+    with open(out_json, "w") as fh:
+        json.dump(res, fh, indent=1)
+    print(json.dumps(res, indent=1))
 
 
 # --------------------------------------------------------------------------- CPU baseline
@@ -285,7 +352,12 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--gradient", action="store_true", help="also time the adjoint gradient workload")
     ap.add_argument("--serving", action="store_true", help="also run the shot-serving workload")
+    ap.add_argument("--copy-probe", action="store_true", help="run a 1 GiB copy (counter scaling reference)")
+    ap.add_argument("--summarize-prof", metavar="DIR", help="summarize rocprofv3 CSV output and exit")
     args = ap.parse_args()
+    if args.summarize_prof:
+        summarize_prof(args.summarize_prof)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is "
@@ -301,6 +373,8 @@ def main():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(2)
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        run_copy_probe()
     fw = run_forward(args)
     out = {
         "metric": "grid-point updates/s (Gpts/s), % of HBM roofline; p50/p99 shot latency",
