@@ -275,7 +275,7 @@ def run_gradient():
         J.backward()
         torch.cuda.synchronize()
         t2 = time.perf_counter()
-        return t1 - t0, t2 - t1, float(J), v.grad
+        return t1 - t0, t2 - t1, float(J.detach()), v.grad
 
     once()
     tf, tb, J, g = once()
@@ -330,7 +330,9 @@ def run_serving(nreq=256, budget_gib=96, sequential=True):
     st.update({"wall_s": round(wall, 2), "budget_gib": budget_gib, "chunk_steps": 32,
                "max_resident_shots": srv.stats["max_resident_shots"],
                "max_resident_gib": round(srv.stats["max_resident_bytes"] / 2 ** 30, 2),
-               "batched_chunks": srv.stats["chunks"]})
+               "batched_chunks": srv.stats["chunks"], "membership_changes": srv.stats["membership_changes"],
+               "gpu_busy_s": round(srv.stats["gpu_busy_s"], 2), "host_admission_s": round(srv.stats["admit_s"], 2),
+               "gpts_per_s_while_busy": round(srv.stats["chunk_points"] / max(srv.stats["gpu_busy_s"], 1e-9) / 1e9, 1)})
     log(f"serving (continuous batching): {st['gpts_per_s']:.1f} Gpts/s, makespan {st['makespan_s']:.2f} s, "
         f"p50 {st['p50_latency_s']:.2f} s, p99 {st['p99_latency_s']:.2f} s, max resident {st['max_resident_shots']}")
     out = {"workload": f"serving_{nreq}req_poisson20_sides128-400_r4_fp32", "batched": st}

@@ -129,4 +129,4 @@ def gradient(v: torch.Tensor, problem: GradientProblem, observed: torch.Tensor):
     traces = WaveProp.apply(v, problem)
     J = misfit(traces, observed)
     J.backward()
-    return float(J), v.grad
+    return float(J.detach()), v.grad

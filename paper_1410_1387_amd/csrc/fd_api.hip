@@ -153,16 +153,37 @@ const AdjEntry *adj_table(fd_dtype dt, int r, int ndim)
     return dt == FD_F32 ? adj_config_f32(r, ndim) : adj_config_f64(r, ndim);
 }
 
-// Planes per z chunk: about two workgroups per CU (256 CUs) resident in one wave of
-// the grid, but at least 4r planes per chunk so the 2r-plane prologue (planes a
-// chunk re-reads from its neighbour) stays a small overhead.
-int choose_zch(int64_t tiles_xy, int64_t nz, int r)
+// Workgroups of kernel k the whole device runs at once (CUs x resident workgroups per
+// CU from the occupancy calculator); 512 if the runtime cannot tell.
+int resident_slots(const void *kernel, int nt)
 {
-    const int64_t target_wgs = 512;
-    int64_t chunks = (target_wgs + tiles_xy - 1) / tiles_xy;
-    chunks = std::min<int64_t>(chunks, std::max<int64_t>(1, nz / (4 * r)));
-    chunks = std::max<int64_t>(1, chunks);
-    return (int)((nz + chunks - 1) / chunks);
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 512;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) return 512;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, nt, 0) != hipSuccess || per_cu <= 0)
+        return 512;
+    return cus * per_cu;
+}
+
+// Planes per z chunk.  More chunks mean more workgroups but each chunk re-reads 2r planes
+// of u^n (its prologue).  Workgroups run in waves of `slots`; with equal-length
+// workgroups a launch costs about ceil(nwg / slots) x (zch + 2r) plane-times, which is
+// minimised over the chunk count.
+int choose_zch(int64_t tiles_xy, int64_t nz, int r, int slots)
+{
+    const int64_t max_chunks = std::max<int64_t>(1, nz / (2 * r));
+    int64_t best_c = 1;
+    double best = 1e300;
+    for (int64_t c = 1; c <= max_chunks; ++c) {
+        const int64_t zch = (nz + c - 1) / c;
+        const int64_t waves = (tiles_xy * c + slots - 1) / slots;
+        const double cost = (double)waves * (double)(zch + 2 * r);
+        if (cost < best - 1e-9) {
+            best = cost;
+            best_c = c;
+        }
+    }
+    return (int)((nz + best_c - 1) / best_c);
 }
 
 }  // namespace
@@ -191,6 +212,7 @@ struct fd_ctx {
     const AdjEntry *ka;
     int zch;
     int64_t tiles_x, tiles_y, chunks_z;
+    int slots;  // resident workgroups of the forward kernel on the device
     int64_t adj_tiles_x, adj_tiles_y, adj_chunks_z;
     int adj_zch;
     std::string cfg_name;
@@ -404,11 +426,13 @@ extern "C" int fd_create(fd_ctx **out, const fd_grid *g, int r, double h, double
     c->ka = ka;
     c->tiles_x = (L.knx + c->kf->bx - 1) / c->kf->bx;
     c->tiles_y = (L.kny + c->kf->by - 1) / c->kf->by;
-    c->zch = tu.zchunk > 0 ? (int)std::min<int64_t>(tu.zchunk, L.knz) : choose_zch(c->tiles_x * c->tiles_y, L.knz, r);
+    c->slots = resident_slots(c->kf->kernel, c->kf->nt);
+    c->zch = tu.zchunk > 0 ? (int)std::min<int64_t>(tu.zchunk, L.knz)
+                           : choose_zch(c->tiles_x * c->tiles_y, L.knz, r, c->slots);
     c->chunks_z = (L.knz + c->zch - 1) / c->zch;
     c->adj_tiles_x = (L.knx + ka->bx - 1) / ka->bx;
     c->adj_tiles_y = (L.kny + ka->by - 1) / ka->by;
-    c->adj_zch = choose_zch(c->adj_tiles_x * c->adj_tiles_y, L.knz, r);
+    c->adj_zch = choose_zch(c->adj_tiles_x * c->adj_tiles_y, L.knz, r, resident_slots(ka->kernel, ka->nt));
     c->adj_chunks_z = (L.knz + c->adj_zch - 1) / c->adj_zch;
     c->nrec = 0;
     c->traces = nullptr;
@@ -829,14 +853,38 @@ extern "C" int fd_batch_set(fd_batch *b, fd_ctx *const *ctxs, const int64_t *tar
     b->target.assign(target, target + nctx);
     b->h_desc.resize((size_t)nctx);
     b->h_prefix.assign((size_t)nctx + 1, 0);
+    // Re-chunk the members for the batch as a whole: the other shots supply parallelism,
+    // so each shot can march longer z chunks (fewer prologue re-reads) than it would
+    // alone.  The cost model is that of choose_zch, summed over the members.
+    int zb = 0;
+    if (nctx > 0) {
+        const int r = ctxs[0]->r, slots = ctxs[0]->slots;
+        static const int cand[] = {512, 384, 256, 192, 128, 96, 64, 48, 32, 24, 16};
+        double best = 1e300;
+        for (int zc : cand) {
+            int64_t nwg = 0, planes = 0;
+            for (int i = 0; i < nctx; ++i) {
+                const int64_t nz = ctxs[i]->L.knz, z = std::min<int64_t>(zc, nz);
+                nwg += ctxs[i]->tiles_x * ctxs[i]->tiles_y * ((nz + z - 1) / z);
+                planes = std::max<int64_t>(planes, z);
+            }
+            const double cost = (double)((nwg + slots - 1) / slots) * (double)(planes + 2 * r);
+            if (cost < best - 1e-9) {
+                best = cost;
+                zb = zc;
+            }
+        }
+    }
     for (int i = 0; i < nctx; ++i) {
         fd_ctx *c = ctxs[i];
         ShotDesc d = c->desc;
         d.ctr[0] = c->step;
         d.ctr[1] = c->step;
         d.target = target[i];
+        d.zch = (int32_t)std::min<int64_t>(zb, c->L.knz);
+        d.chunks_z = (int32_t)((c->L.knz + d.zch - 1) / d.zch);
         b->h_desc[(size_t)i] = d;
-        b->h_prefix[(size_t)i + 1] = b->h_prefix[(size_t)i] + (int32_t)nwg_of(c);
+        b->h_prefix[(size_t)i + 1] = b->h_prefix[(size_t)i] + (int32_t)(c->tiles_x * c->tiles_y * d.chunks_z);
     }
     b->nwg = b->h_prefix[(size_t)nctx];
     b->kf = kf;

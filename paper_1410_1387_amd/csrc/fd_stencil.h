@@ -858,12 +858,14 @@ struct FwdEntry {
     const char *name;
     int bx, by, nt;
     void (*launch)(const LaunchArgs &, int nwg, hipStream_t);
+    const void *kernel;  // the __global__ function (for occupancy queries)
 };
 
 struct AdjEntry {
     const char *name;
     int bx, by, nt;
     void (*launch)(const AdjArgs &, int nwg, hipStream_t);
+    const void *kernel;
 };
 
 template <class C>
@@ -879,15 +881,15 @@ void launch_adj(const AdjArgs &a, int nwg, hipStream_t st)
 }
 
 template <class C>
-constexpr FwdEntry fwd_entry(const char *name)
+FwdEntry fwd_entry(const char *name)
 {
-    return FwdEntry{name, C::BX, C::BY, C::NT, &launch_fwd<C>};
+    return FwdEntry{name, C::BX, C::BY, C::NT, &launch_fwd<C>, reinterpret_cast<const void *>(&fwd_kernel<C>)};
 }
 
 template <class C>
-constexpr AdjEntry adj_entry(const char *name)
+AdjEntry adj_entry(const char *name)
 {
-    return AdjEntry{name, C::BX, C::BY, C::NT, &launch_adj<C>};
+    return AdjEntry{name, C::BX, C::BY, C::NT, &launch_adj<C>, reinterpret_cast<const void *>(&adj_kernel<C>)};
 }
 
 // Implemented in the per-dtype translation units.

@@ -157,7 +157,7 @@ class ShotServer:
         self._stop = threading.Event()
         self.t0 = time.perf_counter()
         self.stats = {"chunks": 0, "membership_changes": 0, "max_resident_bytes": 0, "max_resident_shots": 0,
-                      "gpu_points": 0}
+                      "gpu_points": 0, "gpu_busy_s": 0.0, "chunk_points": 0, "admit_s": 0.0}
         self._error: Optional[BaseException] = None
 
     # ------------------------------------------------------------------ public API
@@ -272,6 +272,7 @@ class ShotServer:
                     if used + need > self.budget:
                         break  # wait for memory: head-of-line order is kept
                     pending.popleft()
+                    t_adm = time.perf_counter()
                     try:
                         ctx, tensors, traces, fp, npts = self._factory.create(req, sstream)
                     except F.FdError as e:
@@ -279,6 +280,7 @@ class ShotServer:
                         continue
                     for t in tensors + [traces]:  # written by batched kernels on bstream
                         t.record_stream(bstream)
+                    self.stats["admit_s"] += time.perf_counter() - t_adm
                     active.append(_Live(req, ctx, tensors, traces, fp, npts, arrival, self.now(), fut))
                     used += fp
                     dirty = True
@@ -301,15 +303,20 @@ class ShotServer:
                     dirty = False
                     if not active:
                         continue
+                before = {id(s): F.fd_get_step(s.ctx) for s in active}
+                ev0 = torch.cuda.Event(enable_timing=True)
+                ev0.record(bstream)
                 F.fd_batch_step(batch, self.chunk)
-                ev = torch.cuda.Event()
+                ev = torch.cuda.Event(enable_timing=True)
                 ev.record(bstream)
+                pts = sum((F.fd_get_step(s.ctx) - before[id(s)]) * (s.npoints // max(1, s.req.nsteps))
+                          for s in active)
                 finishing = [s for s in active if F.fd_get_step(s.ctx) >= s.req.nsteps and not s.future.done()
                              and not getattr(s, "_queued_done", False)]
                 for s in finishing:
                     s._queued_done = True
                     self.stats["gpu_points"] += s.npoints
-                inflight.append((ev, finishing))
+                inflight.append((ev, finishing, ev0, pts))
                 self.stats["chunks"] += 1
                 if len(inflight) > 1:
                     if self._retire_done(inflight, wait_all=False):
@@ -327,9 +334,11 @@ class ShotServer:
         but the newest).  Returns True if any shot completed."""
         any_done = False
         while inflight and (wait_all or len(inflight) > 1):
-            ev, finishing = inflight.popleft()
+            ev, finishing, ev0, pts = inflight.popleft()
             ev.synchronize()
             now = self.now()
+            self.stats["gpu_busy_s"] += ev0.elapsed_time(ev) / 1e3
+            self.stats["chunk_points"] += pts
             for s in finishing:
                 s.future.set_result(ShotResult(s.req.rid, "ok", s.traces, s.arrival, s.admitted, now, s.npoints))
                 self._outstanding.discard(s.future)
