@@ -25,6 +25,11 @@ Finite-differences on multi-threaded architectures using OCCA") defines it:
   with p = q), zero values for r points outside the domain (Sec. 1, last
   paragraph), or a periodic box for closed-form tests.  Implemented in
   ``fd_oracle.c`` as plain loops.
+* ``z_weights``, ``vti_dt_max``, ``vti_forward`` -- the two-field VTI propagator
+  of Sec. 1 (eqs. (p) and (q)): p and q advanced together by the centred time
+  scheme, the symmetric radius-Rxy xy stencil acting on p, and a per-plane
+  2Rz+1-point z stencil acting on q whose weights absorb a variable spacing
+  dz_k (Sec. 1).  ``vti_oracle.c`` holds the loops.
 * ``gradient``  -- the discrete adjoint (Lagrange multiplier recursion of the
   forward scheme) of J = 1/2 sum (traces - observed)^2 with respect to v.
   Not in the paper; its statement of the problem names full waveform inversion
@@ -45,7 +50,7 @@ from functools import lru_cache
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "fd_oracle.c")
+_SRCS = [os.path.join(_HERE, "fd_oracle.c"), os.path.join(_HERE, "vti_oracle.c")]
 _LIB = os.path.join(_HERE, "libfd_oracle.so")
 
 __all__ = [
@@ -59,6 +64,10 @@ __all__ = [
     "gradient",
     "misfit",
     "linear_index",
+    "z_weights_exact",
+    "z_weights",
+    "vti_dt_max",
+    "vti_forward",
 ]
 
 
@@ -66,14 +75,14 @@ __all__ = [
 
 
 def build(force: bool = True) -> str:
-    """Compile fd_oracle.c with gcc (IEEE FP64: no fast-math, no FMA contraction)."""
-    if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
+    """Compile the C sources with gcc (IEEE FP64: no fast-math, no FMA contraction)."""
+    if not force and os.path.exists(_LIB) and all(os.path.getmtime(_LIB) >= os.path.getmtime(f) for f in _SRCS):
         return _LIB
     tmp = _LIB + ".tmp"
     cmd = [
         "gcc", "-O3", "-std=c11", "-fPIC", "-shared", "-fopenmp",
         "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wextra",
-        _SRC, "-o", tmp, "-lm",
+        *_SRCS, "-o", tmp, "-lm",
     ]
     subprocess.run(cmd, check=True)
     os.replace(tmp, _LIB)
@@ -100,7 +109,11 @@ def _lib():
             ctypes.c_int, P, ctypes.c_int, P, ctypes.c_double, ctypes.c_double, P, ctypes.c_int,
             I64, I64, P, P, P, P,
         ]
-        for f in (lib.fdo_laplacian, lib.fdo_forward, lib.fdo_adjoint):
+        lib.fdo_vti_forward.argtypes = [
+            P, ctypes.c_int, ctypes.c_int, P, P, P, ctypes.c_double, ctypes.c_double, P, P, P, ctypes.c_int,
+            ctypes.c_int, I64, I64, P, P, P, I64, P, P, P, P, P, P, P,
+        ]
+        for f in (lib.fdo_laplacian, lib.fdo_forward, lib.fdo_adjoint, lib.fdo_vti_forward):
             f.restype = ctypes.c_int
         _lib_handle = lib
     return _lib_handle
@@ -137,14 +150,20 @@ def weights(r: int) -> tuple[Fraction, ...]:
     """
     if not (1 <= r <= 16):
         raise ValueError("r must be in [1, 16]")
-    nunk = r + 1
     rows = []
     for k in range(r + 1):
         row = [Fraction(1 if k == 0 else 0)]  # coefficient of w0: 0^{2k}
         row += [Fraction(2 * l ** (2 * k)) for l in range(1, r + 1)]
         rhs = Fraction(2) if k == 1 else Fraction(0)
         rows.append(row + [rhs])
-    # Gauss-Jordan elimination with exact pivots.
+    return tuple(_solve_exact(rows))
+
+
+def _solve_exact(rows):
+    """Solution of the square system given as augmented rows [a_0 .. a_{n-1} | b],
+    by Gauss-Jordan elimination over the rationals (exact pivots)."""
+    rows = [list(r) for r in rows]
+    nunk = len(rows)
     for col in range(nunk):
         piv = next(i for i in range(col, nunk) if rows[i][col] != 0)
         rows[col], rows[piv] = rows[piv], rows[col]
@@ -154,7 +173,7 @@ def weights(r: int) -> tuple[Fraction, ...]:
             if i != col and rows[i][col] != 0:
                 f = rows[i][col]
                 rows[i] = [a - f * b for a, b in zip(rows[i], rows[col])]
-    return tuple(rows[i][nunk] for i in range(nunk))
+    return [rows[i][nunk] for i in range(nunk)]
 
 
 def weights_f64(r: int) -> np.ndarray:
@@ -309,3 +328,133 @@ def gradient(v, h, dt, r, nsteps, sources, receivers, observed, periodic=False):
         "grad_v": 2.0 * v * grad_m,
         "traces": fw["traces"],
     }
+
+
+# --------------------------------------------------------------------------- VTI propagator
+
+
+@lru_cache(maxsize=None)
+def _z_weights_cached(zc: tuple, rz: int) -> tuple:
+    nz = len(zc) - 2 * rz
+    table = []
+    for k in range(nz):
+        zk = zc[k + rz]
+        d = [zc[k + rz + l] - zk for l in range(-rz, rz + 1)]
+        # moments: sum_l w_l d_l^m = (d^2/dz^2) (z - z_k)^m at z_k = 2 if m == 2 else 0
+        rows = [[di ** m for di in d] + [Fraction(2 if m == 2 else 0)] for m in range(2 * rz + 1)]
+        table.append(tuple(_solve_exact(rows)))
+    return tuple(table)
+
+
+def z_weights_exact(zc, rz: int) -> tuple:
+    """Per-plane second-derivative weights of the z stencil of Sec. 1: for plane k the
+    2rz+1 weights w_{k,l} (l = -rz..rz) of the unique stencil on the planes k-rz..k+rz
+    that differentiates every polynomial of degree <= 2rz exactly at z_k, as exact
+    fractions.  zc holds the coordinates of planes -rz .. nz+rz-1 (the rz ghost planes
+    on each side included), strictly increasing; each double is taken exactly."""
+    zc = tuple(Fraction(float(z)) for z in zc)
+    if len(zc) < 2 * rz + 1 or any(b <= a for a, b in zip(zc, zc[1:])):
+        raise ValueError("z coordinates must be strictly increasing, nz >= 1")
+    return _z_weights_cached(zc, int(rz))
+
+
+def z_weights(zc, rz: int) -> np.ndarray:
+    """z_weights_exact rounded to doubles, as an [nz][2rz+1] array."""
+    return np.array([[float(w) for w in row] for row in z_weights_exact(zc, rz)], dtype=np.float64)
+
+
+def uniform_z(nz: int, rz: int, dz: float) -> np.ndarray:
+    """Coordinates of planes -rz .. nz+rz-1 of a uniform z grid (plane 0 at z = 0)."""
+    return np.arange(-rz, nz + rz, dtype=np.float64) * dz
+
+
+def _cell_dz(zc, rz: int) -> np.ndarray:
+    """z extent of the cell of plane k: half the distance between its two neighbours
+    (the spacing itself on a uniform grid)."""
+    zc = np.asarray(zc, dtype=np.float64)
+    nz = zc.shape[0] - 2 * rz
+    k = np.arange(nz) + rz
+    return 0.5 * (zc[k + 1] - zc[k - 1])
+
+
+def vti_dt_max(rxy: int, rz: int, h: float, wz: np.ndarray, vz, eps, delta) -> float:
+    """Largest stable time step.  For constant coefficients a Fourier mode on which
+    -(Dxx + Dyy) and -Dzz act as the numbers a_xy and a_z obeys the 2x2 recursion with
+        M = [[nux2 a_xy, nuz2 a_z], [nun2 a_xy, nuz2 a_z]],
+    stable iff every eigenvalue of M lies in [0, 4/dt^2].  M has non-negative entries, so
+    its largest eigenvalue grows with each entry: it is largest at a_xy = 2 S_xy / h^2
+    (both axes at the Nyquist point) and the largest a_z, bounded by the largest row sum
+    of |wz| (exact on a uniform grid).  The smaller eigenvalue is negative when
+    nun2 > nux2 (delta > eps); no time step is stable then and 0.0 is returned."""
+    w = weights(rxy)
+    sxy = float(-w[0] - 2 * sum(w[l] * (-1) ** l for l in range(1, rxy + 1)))
+    axy = 2.0 * sxy / (h * h)
+    az = float(np.max(np.sum(np.abs(np.asarray(wz, dtype=np.float64)), axis=1)))
+    vz = np.asarray(vz, dtype=np.float64)
+    nuz2 = vz * vz
+    nux2 = nuz2 * (1.0 + 2.0 * np.asarray(eps, dtype=np.float64))
+    nun2 = nuz2 * (1.0 + 2.0 * np.asarray(delta, dtype=np.float64))
+    if np.any(nun2 > nux2):
+        return 0.0
+    a, b, c = nux2 * axy, nuz2 * az, nun2 * axy
+    lam = 0.5 * ((a + b) + np.sqrt((a - b) ** 2 + 4.0 * b * c))
+    return float(2.0 / math.sqrt(float(np.max(lam))))
+
+
+def vti_forward(vz, eps, delta, h, dt, rxy, rz, nsteps, zc=None, sources=(), receivers=None,
+                periodic_xy=False, periodic_z=False, state=None):
+    """Run ``nsteps`` steps of the VTI scheme (Sec. 1, eqs. (p), (q)).
+
+    vz, eps, delta  dense (nz, ny, nx) models: vertical velocity (m/s) and the two
+                    anisotropy parameters
+    zc              coordinates of planes -rz .. nz+rz-1 (default: uniform, spacing h)
+    sources         sequence of ((x, y, z), samples, amp_p, amp_q): sample n enters the
+                    step producing level n+1, scaled by dt^2 / (h^2 dz_k)
+    receivers       int array [nrec, 3] of (x, y, z); traces[n][j] = field^{n+1}(x_j)
+    state           optional (p0, pm1, q0, qm1), default zero
+
+    Returns dict(p, p_prev, q, q_prev, traces_p, traces_q).
+    """
+    vz = np.ascontiguousarray(vz, dtype=np.float64)
+    shape = vz.shape
+    if len(shape) != 3:
+        raise ValueError("the VTI propagator is three-dimensional")
+    nz = shape[0]
+    _, n = _dims(shape)
+    eps = np.ascontiguousarray(np.broadcast_to(eps, shape), dtype=np.float64)
+    delta = np.ascontiguousarray(np.broadcast_to(delta, shape), dtype=np.float64)
+    if zc is None:
+        zc = uniform_z(nz, rz, h)
+    zc = np.asarray(zc, dtype=np.float64)
+    if zc.shape[0] != nz + 2 * rz:
+        raise ValueError("zc must hold nz + 2 rz plane coordinates")
+    wz = np.ascontiguousarray(z_weights(zc, rz))
+    dzc = np.ascontiguousarray(_cell_dz(zc, rz))
+    wxy = weights_f64(rxy)
+    if state is None:
+        p, pm, q, qm = (np.zeros(shape) for _ in range(4))
+    else:
+        p, pm, q, qm = (np.array(a, dtype=np.float64, copy=True) for a in state)
+    sources = list(sources)
+    nsrc = len(sources)
+    src_idx = np.zeros(nsrc, dtype=np.int64)
+    src = np.zeros((nsteps, nsrc), dtype=np.float64)
+    amp = np.zeros((nsrc, 2), dtype=np.float64)
+    for e, (pos, wav, ap, aq) in enumerate(sources):
+        src_idx[e] = linear_index(shape, [pos])[0]
+        wav = np.asarray(wav, dtype=np.float64)
+        k = min(nsteps, wav.shape[0])
+        src[:k, e] = wav[:k]
+        amp[e] = (ap, aq)
+    rec_idx = np.zeros(0, dtype=np.int64) if receivers is None or len(receivers) == 0 else \
+        linear_index(shape, receivers)
+    trp = np.zeros((nsteps, rec_idx.shape[0]))
+    trq = np.zeros((nsteps, rec_idx.shape[0]))
+    st = _lib().fdo_vti_forward(
+        _ptr(n), int(rxy), int(rz), _ptr(wxy), _ptr(wz), _ptr(dzc), float(h), float(dt), _ptr(vz), _ptr(eps),
+        _ptr(delta), int(periodic_xy), int(periodic_z), int(nsteps), nsrc, _ptr(src_idx),
+        _ptr(np.ascontiguousarray(src)), _ptr(amp), int(rec_idx.shape[0]), _ptr(rec_idx), _ptr(trp), _ptr(trq),
+        _ptr(p), _ptr(pm), _ptr(q), _ptr(qm),
+    )
+    _check(st, "vti_forward")
+    return {"p": p, "p_prev": pm, "q": q, "q_prev": qm, "traces_p": trp, "traces_q": trq}
