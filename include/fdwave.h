@@ -81,7 +81,8 @@ typedef struct {
 /* Exact central weights of the radius-r second-derivative stencil on a unit grid,
  * h^2 u'' ~ w[0] u_i + sum_{l=1..r} w[l] (u_{i+l} + u_{i-l})  (Sec. 1, stencil form;
  * the weights are those exact for polynomials of degree <= 2r+1).
- * w: host, r+1 doubles, written.  1 <= r <= 8. */
+ * w: host, r+1 doubles, written.  1 <= r <= 12 (the acoustic kernels take r <= 8,
+ * the VTI xy stencil r <= 12).  Each weight is the correctly rounded double. */
 int fd_weights(int r, double *w);
 
 /* Von Neumann limit of the leapfrog scheme for this stencil:
@@ -257,6 +258,87 @@ const char *fd_kernel_config(const fd_ctx *ctx);
 int fd_set_tuning(fd_dtype dtype, int r, int ndim, int config, int zchunk);
 
 const char *fd_last_error(void);
+
+/* ================================================================= VTI propagator
+ *
+ * The two-field pseudo-acoustic VTI equations of Sec. 1, eqs. (p) and (q), advanced with
+ * the centred time scheme of Sec. 1 on a 3-D grid:
+ *   p^{n+1} = 2p^n - p^{n-1} + dt^2 [nu_x^2 (Dxx + Dyy) p^n + nu_z^2 Dzz q^n] + dt^2 amp_p s[n] / (h^2 dz_k)
+ *   q^{n+1} = 2q^n - q^{n-1} + dt^2 [nu_n^2 (Dxx + Dyy) p^n + nu_z^2 Dzz q^n] + dt^2 amp_q s[n] / (h^2 dz_k)
+ * with nu_z = vz, nu_x = vz sqrt(1 + 2 eps), nu_n = vz sqrt(1 + 2 delta) (Sec. 1).
+ *   - Dxx + Dyy: the symmetric radius-rxy xy stencil of Sec. 1 with spacing h, weights
+ *     fd_weights(rxy) per axis (centre weight 2 w[0]).
+ *   - Dzz: the per-plane z stencil of Sec. 1, 2rz+1 weights per plane (fd_vti_z_weights),
+ *     which absorb a variable z spacing.
+ *   - Zero values for rxy points outside the domain in x and y and rz planes in z.
+ *   - dz_k = (z_{k+1} - z_{k-1}) / 2, the z extent of the cell of plane k (dz on a
+ *     uniform grid).
+ * Supported radius pairs (rxy, rz): rxy in {2, 4, 8, 12}, rz in {1, 2, 4, 8}, rz <= rxy.
+ * Same conventions as the acoustic context: caller-owned device memory, one stream,
+ * asynchronous stepping, fd_status codes. */
+
+typedef struct fd_vti_ctx fd_vti_ctx;
+
+/* Second-derivative weights of the z stencil of Sec. 1 for every plane: w[k*(2rz+1) + l+rz]
+ * multiplies q at plane k+l (l = -rz..rz) and the row is exact for every polynomial of
+ * degree <= 2rz at z_k.  Computed in FP64 with Fornberg's recursion (Math. Comp. 51, 1988).
+ * zc: host, nz + 2rz strictly increasing plane coordinates (planes -rz .. nz+rz-1, in m).
+ * w: host, nz * (2rz+1) doubles (1/m^2), written.  1 <= rz <= 8. */
+int fd_vti_z_weights(const double *zc, int64_t nz, int rz, double *w);
+
+/* Largest stable dt for a model bounded by vz <= vz_max, eps <= eps_max, delta <= delta_max
+ * (delta <= eps point-wise): 2 / sqrt(lambda), lambda the largest eigenvalue of the 2x2
+ * mode matrix [[nu_x^2 a, nu_z^2 b], [nu_n^2 a, nu_z^2 b]] at a = 2 S_xy / h^2 (Nyquist in
+ * x and y) and b = the largest row sum of |Dzz| (exact for constant coefficients on a
+ * uniform grid).  zc as in fd_vti_z_weights, or NULL for a uniform spacing h.
+ * Returns -1 on invalid arguments. */
+double fd_vti_dt_max(int rxy, int rz, double h, const double *zc, int64_t nz, double vz_max, double eps_max,
+                     double delta_max);
+
+/* Device workspace for fd_vti_create: seven padded fields (p, q at two time levels, three
+ * coefficient fields), the z weight table and the source/receiver tables. */
+int fd_vti_workspace_bytes(const fd_grid *g, int rxy, int rz, fd_dtype dtype, int64_t max_sources,
+                           int64_t max_receivers, size_t *bytes);
+
+/* Create a VTI context.  g: ndim 3.  zc: host, nz + 2rz plane coordinates, or NULL for a
+ * uniform z spacing h.  vz, eps, delta: device, dtype, dense [nz][ny][nx], read during the
+ * call only.  Errors: FD_E_INVAL (bad grid, radius pair, spacing, model: vz <= 0, 1 + 2 eps
+ * <= 0, 1 + 2 delta < 0, non-finite); FD_E_UNSTABLE if delta > eps anywhere (the coupled
+ * system then has a growing mode for every dt) or dt exceeds the limit of
+ * fd_vti_dt_max evaluated point-wise; FD_E_NOMEM if ws_bytes is too small. */
+int fd_vti_create(fd_vti_ctx **out, const fd_grid *g, int rxy, int rz, double h, const double *zc, double dt,
+                  const void *vz, const void *eps, const void *delta, fd_dtype dtype, void *workspace,
+                  size_t ws_bytes, int64_t max_sources, int64_t max_receivers, void *stream);
+int fd_vti_destroy(fd_vti_ctx *ctx);
+
+/* Point source: sample n of wavelet (device, dtype, nsamp samples, borrowed) enters the
+ * step producing level n+1, scaled by dt^2 amp_p / (h^2 dz_k) in p and dt^2 amp_q /
+ * (h^2 dz_k) in q.  Eq. (p) of Sec. 1 forces p only: amp_p = 1, amp_q = 0. */
+int fd_vti_inject(fd_vti_ctx *ctx, const void *wavelet, int64_t nsamp, const int64_t pos[3], double amp_p,
+                  double amp_q);
+
+/* Receivers: pos host int32 [nrec][3]; traces_p[n][j] = p^{n+1} and traces_q[n][j] = q^{n+1}
+ * at receiver j (device, dtype, time-major [cap][nrec]; either may be NULL), counted from
+ * the step at which fd_vti_record is called. */
+int fd_vti_record(fd_vti_ctx *ctx, const int32_t *pos, int64_t nrec, void *traces_p, void *traces_q,
+                  int64_t cap);
+
+/* nsteps steps, enqueued on the context stream. */
+int fd_vti_step(fd_vti_ctx *ctx, int64_t nsteps);
+int fd_vti_sync(fd_vti_ctx *ctx);
+int fd_vti_get_step(const fd_vti_ctx *ctx, int64_t *step);
+
+/* Dense copies (device, dtype, [nz][ny][nx]) of p^n, p^{n-1}, q^n, q^{n-1}; any may be NULL
+ * (set_state: that field keeps its buffer, which is only valid if step has the parity of
+ * the current step; otherwise all four are required, FD_E_INVAL). */
+int fd_vti_get_state(fd_vti_ctx *ctx, void *p, void *p_prev, void *q, void *q_prev);
+int fd_vti_set_state(fd_vti_ctx *ctx, const void *p, const void *p_prev, const void *q, const void *q_prev,
+                     int64_t step);
+
+/* Kernel tile configuration in use, and the tuning override (config index, z chunk; 0 = auto)
+ * for contexts created afterwards. */
+const char *fd_vti_kernel_config(const fd_vti_ctx *ctx);
+int fd_vti_set_tuning(fd_dtype dtype, int rxy, int rz, int config, int zchunk);
 
 #ifdef __cplusplus
 }

@@ -19,6 +19,7 @@
 #include "fd_stencil.h"
 #include "fd_types.h"
 #include "fd_util.h"
+#include "fd_host.h"
 
 using namespace fdw;
 
@@ -31,7 +32,8 @@ using namespace fdw;
 
 static thread_local std::string g_last_error;
 
-static int fail(int code, const char *fmt, ...)
+namespace fdw {
+int host_fail(int code, const char *fmt, ...)
 {
     char buf[512];
     va_list ap;
@@ -41,6 +43,9 @@ static int fail(int code, const char *fmt, ...)
     g_last_error = buf;
     return code;
 }
+}  // namespace fdw
+
+#define fail fdw::host_fail
 
 #define HIP_TRY(ctxp, expr)                                                                      \
     do {                                                                                         \
@@ -153,6 +158,10 @@ const AdjEntry *adj_table(fd_dtype dt, int r, int ndim)
     return dt == FD_F32 ? adj_config_f32(r, ndim) : adj_config_f64(r, ndim);
 }
 
+}  // namespace
+
+namespace fdw {
+
 // Workgroups of kernel k the whole device runs at once (CUs x resident workgroups per
 // CU from the occupancy calculator); 512 if the runtime cannot tell.
 int resident_slots(const void *kernel, int nt)
@@ -186,7 +195,7 @@ int choose_zch(int64_t tiles_xy, int64_t nz, int r, int slots)
     return (int)((nz + best_c - 1) / best_c);
 }
 
-}  // namespace
+}  // namespace fdw
 
 // ------------------------------------------------------------------ context
 
@@ -323,7 +332,7 @@ static int upload_tables(fd_ctx *c)
 
 extern "C" int fd_weights(int r, double *w)
 {
-    if (r < 1 || r > 8 || !w) return fail(FD_E_INVAL, "fd_weights: r must be in [1, 8]");
+    if (r < 1 || r > 12 || !w) return fail(FD_E_INVAL, "fd_weights: r must be in [1, 12]");
     double s = 0.0;
     for (int l = 1; l <= r; ++l) {
         w[l] = stencil_weight(r, l);

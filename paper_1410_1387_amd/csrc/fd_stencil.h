@@ -46,21 +46,29 @@ namespace fdw {
 
 // ------------------------------------------------------------------ weights
 
-constexpr double factorial(int n)
+constexpr unsigned __int128 gcd_u128(unsigned __int128 a, unsigned __int128 b)
 {
-    double f = 1.0;
-    for (int i = 2; i <= n; ++i) f *= (double)i;
-    return f;
+    while (b != 0) {
+        const unsigned __int128 t = a % b;
+        a = b;
+        b = t;
+    }
+    return a;
 }
 
 // Exact central weight of the radius-r second-derivative stencil:
-// w_l = 2 (-1)^{l+1} (r!)^2 / (l^2 (r-l)! (r+l)!).  For r <= 8 the numerator and
-// denominator are integers below 2^53, so the single division is correctly rounded.
+// w_l = 2 (-1)^{l+1} (r!)^2 / (l^2 (r-l)! (r+l)!) = 2 (-1)^{l+1} [r!/(r-l)!] / (l^2 [(r+l)!/r!]).
+// The fraction is reduced in 128-bit integers; for r <= 12 its reduced numerator and
+// denominator are below 2^53, so the one division is correctly rounded.
 constexpr double stencil_weight(int r, int l)
 {
-    double num = 2.0 * factorial(r) * factorial(r);
-    double den = (double)l * (double)l * factorial(r - l) * factorial(r + l);
-    double w = num / den;
+    unsigned __int128 num = 2, den = (unsigned __int128)(l * l);
+    for (int i = r - l + 1; i <= r; ++i) num *= (unsigned)i;
+    for (int i = r + 1; i <= r + l; ++i) den *= (unsigned)i;
+    const unsigned __int128 g = gcd_u128(num, den);
+    num /= g;
+    den /= g;
+    const double w = (double)(uint64_t)num / (double)(uint64_t)den;
     return (l % 2 == 1) ? w : -w;
 }
 

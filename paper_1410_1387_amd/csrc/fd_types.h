@@ -71,4 +71,33 @@ struct AdjArgs {
     int32_t tiles_x, tiles_y, chunks_z, pad0;
 };
 
+// ------------------------------------------------------------------ VTI propagator
+
+// One point source of the two-field VTI propagator: sample n of `wav` times scale_p
+// (scale_q) = amp_p (amp_q) * dt^2 / (h^2 dz_k) is added to p^{n+1} (q^{n+1}).
+struct VtiSource {
+    const void *wav;
+    int64_t nsamp;
+    double scale_p, scale_q;
+};
+
+// Everything one VTI launch reads (passed by value as the kernel argument).
+struct VtiDesc {
+    void *pbuf[2];         // padded p fields: p^n is pbuf[n & 1], p^{n+1} overwrites pbuf[(n+1) & 1]
+    void *qbuf[2];         // the same for q
+    const void *ax;        // dt^2 nu_x^2 / h^2   (padded)
+    const void *an;        // dt^2 nu_n^2 / h^2
+    const void *az;        // dt^2 nu_z^2 / h^2
+    const void *wz;        // [nz][2 RZ + 1] z weights times h^2
+    int32_t nx, ny, nz;
+    int32_t tiles_x, tiles_y, chunks_z, zch, xcd_remap;
+    int64_t px, pxy, off0;
+    const int32_t *ev_ptr; // CSR over (x, y) columns, as for the acoustic kernel
+    const Event *ev;
+    const VtiSource *src;
+    void *traces_p;        // [cap][nrec] or null
+    void *traces_q;
+    int64_t nrec, rec_base, rec_cap;
+};
+
 }  // namespace fdw

@@ -25,4 +25,12 @@ hipError_t launch_grad_finish(int dtype, const Geom &g, const void *gpad, const 
                               hipStream_t st);
 hipError_t launch_copy_probe(void *dst, const void *src, size_t bytes, hipStream_t st);
 
+// VTI model preparation: from dense vz, eps, delta write ax, an, az = k nu^2 (k = dt^2/h^2)
+// into the padded layout and reduce, over all points, the largest eigenvalue of the
+// mode matrix [[nu_x^2 a, nu_z^2 b], [nu_n^2 a, nu_z^2 b]] and two flags (invalid model
+// value; delta > eps) into out[0..2].  partial holds 3 * kPrepBlocks doubles.
+hipError_t launch_vti_prep(int dtype, const Geom &g, const void *vz, const void *eps, const void *delta, void *ax,
+                           void *an, void *az, double k, double a, double b, double *partial, double *out,
+                           hipStream_t st);
+
 }  // namespace fdw

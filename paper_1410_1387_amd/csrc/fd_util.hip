@@ -144,6 +144,77 @@ __global__ void grad_finish_kernel(Geom g, const T *__restrict__ gpad, const T *
         out[i] = (T)(scale * 2.0 * (double)gpad[padded_offset(g, i)] / (double)v[i]);
 }
 
+// VTI model preparation (see launch_vti_prep).  lam is the larger root of
+// x^2 - (A + B) x + B (A - C) with A = nu_x^2 a, B = nu_z^2 b, C = nu_n^2 a.
+template <typename T>
+__global__ void vti_prep_kernel(Geom g, const T *__restrict__ vz, const T *__restrict__ eps,
+                                const T *__restrict__ delta, T *__restrict__ ax, T *__restrict__ an,
+                                T *__restrict__ az, double k, double a, double b, double *__restrict__ partial)
+{
+    __shared__ double s0[kThreads], s1[kThreads], s2[kThreads];
+    const int64_t n = (int64_t)g.nx * g.ny * g.nz;
+    double lam = 0.0, bad = 0.0, anis = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double v = (double)vz[i], e = (double)eps[i], d = (double)delta[i];
+        const double fx = 1.0 + 2.0 * e, fn = 1.0 + 2.0 * d;
+        if (!(v > 0.0) || !isfinite(v) || !(fx > 0.0) || !isfinite(fx) || !(fn >= 0.0) || !isfinite(fn)) bad = 1.0;
+        if (d > e) anis = 1.0;
+        const double z2 = v * v, x2 = z2 * fx, n2 = z2 * fn;
+        const double A = x2 * a, B = z2 * b, C = n2 * a;
+        const double l = 0.5 * ((A + B) + sqrt((A - B) * (A - B) + 4.0 * B * C));
+        lam = fmax(lam, l);
+        const int64_t o = padded_offset(g, i);
+        ax[o] = (T)(k * x2);
+        an[o] = (T)(k * n2);
+        az[o] = (T)(k * z2);
+    }
+    s0[threadIdx.x] = lam;
+    s1[threadIdx.x] = bad;
+    s2[threadIdx.x] = anis;
+    __syncthreads();
+    for (int s = kThreads / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            s0[threadIdx.x] = fmax(s0[threadIdx.x], s0[threadIdx.x + s]);
+            s1[threadIdx.x] = fmax(s1[threadIdx.x], s1[threadIdx.x + s]);
+            s2[threadIdx.x] = fmax(s2[threadIdx.x], s2[threadIdx.x + s]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partial[3 * blockIdx.x] = s0[0];
+        partial[3 * blockIdx.x + 1] = s1[0];
+        partial[3 * blockIdx.x + 2] = s2[0];
+    }
+}
+
+__global__ void max3_final(const double *__restrict__ partial, int nb, double *__restrict__ out)
+{
+    __shared__ double s0[kThreads], s1[kThreads], s2[kThreads];
+    double m0 = 0.0, m1 = 0.0, m2 = 0.0;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+        m0 = fmax(m0, partial[3 * i]);
+        m1 = fmax(m1, partial[3 * i + 1]);
+        m2 = fmax(m2, partial[3 * i + 2]);
+    }
+    s0[threadIdx.x] = m0;
+    s1[threadIdx.x] = m1;
+    s2[threadIdx.x] = m2;
+    __syncthreads();
+    for (int s = kThreads / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            s0[threadIdx.x] = fmax(s0[threadIdx.x], s0[threadIdx.x + s]);
+            s1[threadIdx.x] = fmax(s1[threadIdx.x], s1[threadIdx.x + s]);
+            s2[threadIdx.x] = fmax(s2[threadIdx.x], s2[threadIdx.x + s]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = s0[0];
+        out[1] = s1[0];
+        out[2] = s2[0];
+    }
+}
+
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 __global__ void copy_probe_kernel(f4 *__restrict__ dst, const f4 *__restrict__ src, int64_t n)
@@ -224,6 +295,24 @@ hipError_t launch_grad_finish(int dtype, const Geom &g, const void *gpad, const 
     else
         hipLaunchKernelGGL(grad_finish_kernel<double>, dim3(nb), dim3(kThreads), 0, st, g, (const double *)gpad,
                            (const double *)v, (double *)out, scale);
+    return hipGetLastError();
+}
+
+hipError_t launch_vti_prep(int dtype, const Geom &g, const void *vz, const void *eps, const void *delta, void *ax,
+                           void *an, void *az, double k, double a, double b, double *partial, double *out,
+                           hipStream_t st)
+{
+    const int64_t n = (int64_t)g.nx * g.ny * g.nz;
+    const int nb = blocks_for(n, kPrepBlocks);
+    if (dtype == 0)
+        hipLaunchKernelGGL(vti_prep_kernel<float>, dim3(nb), dim3(kThreads), 0, st, g, (const float *)vz,
+                           (const float *)eps, (const float *)delta, (float *)ax, (float *)an, (float *)az, k, a, b,
+                           partial);
+    else
+        hipLaunchKernelGGL(vti_prep_kernel<double>, dim3(nb), dim3(kThreads), 0, st, g, (const double *)vz,
+                           (const double *)eps, (const double *)delta, (double *)ax, (double *)an, (double *)az, k,
+                           a, b, partial);
+    hipLaunchKernelGGL(max3_final, dim3(1), dim3(kThreads), 0, st, (const double *)partial, nb, out);
     return hipGetLastError();
 }
 

@@ -1,6 +1,7 @@
-"""Writes the kernel-registry translation units fd_fwd_{f32,f64}.hip and
-fd_adj_{f32,f64}.hip: explicit template instantiations of the stencil kernels and the
-(radius, ndim) -> tile-configuration tables the host side dispatches on.
+"""Writes the kernel-registry translation units fd_fwd_{f32,f64}.hip,
+fd_adj_{f32,f64}.hip and fd_vti_{f32,f64}.hip: explicit template instantiations of the
+stencil kernels and the (radius, ndim) -> tile-configuration tables (for the VTI
+kernel: (xy radius, z radius) -> tiles) the host side dispatches on.
 
 Tile shapes are (threads along x, threads along y, rows per thread); the first entry
 of each list is the default.  Rerun after editing the lists:
@@ -21,6 +22,12 @@ F64_SWEEP_RADII = {4}
 F2D = (64, 1, 1)          # 2-D forward and adjoint: one row of 64 threads
 ADJ_F32_3D = (16, 16, 1)
 ADJ_F64_3D = (32, 8, 1)
+# VTI kernel: (xy radius, z radius) pairs and tile shapes (threads along x, rows along y)
+VTI_RADII = [(2, 1), (2, 2), (4, 1), (4, 2), (4, 4), (8, 1), (8, 2), (8, 4), (8, 8),
+             (12, 1), (12, 2), (12, 4), (12, 8)]
+VTI_F32 = [(16, 16), (32, 8), (16, 8), (32, 16)]
+VTI_F64 = [(16, 16), (32, 8)]
+VTI_SWEEP = {(12, 8), (4, 4)}
 
 HDR = """// {fname} -- explicit instantiations of the {what} stencil kernels for {T}
 // and the (radius, ndim) -> tile-configuration table the host side dispatches on.
@@ -81,8 +88,31 @@ def adj_file(T, d3):
         f.write(out)
 
 
+def vti_file(T, tiles):
+    tag = "f32" if T == "float" else "f64"
+    vec = 4 if T == "float" else 2
+    out = HDR.format(fname=f"fd_vti_{tag}.hip", what="VTI", T=T).replace('#include "fd_stencil.h"',
+                                                                         '#include "fd_vti.h"')
+    for (rxy, rz) in VTI_RADII:
+        lst = tiles if (rxy, rz) in VTI_SWEEP else tiles[:1]
+        out += f"static const VtiEntry v_{rxy}_{rz}[] = {{\n"
+        for (txn, tyn) in lst:
+            name = f"{tag} vti rxy{rxy} rz{rz} tile {txn * vec}x{tyn} ({txn * tyn} thr)"
+            out += f'    vti_entry<VtiCfg<{T}, {rxy}, {rz}, {txn}, {tyn}>>("{name}"),\n'
+        out += "};\n"
+    out += "\nconst VtiEntry *vti_configs_" + tag + "(int rxy, int rz, int *count)\n{\n    switch (rxy * 100 + rz) {\n"
+    for (rxy, rz) in VTI_RADII:
+        out += (f"    case {rxy * 100 + rz}: *count = (int)(sizeof(v_{rxy}_{rz}) / sizeof(VtiEntry)); "
+                f"return v_{rxy}_{rz};\n")
+    out += "    default: *count = 0; return nullptr;\n    }\n}\n\n}  // namespace fdw\n"
+    with open(os.path.join(HERE, f"fd_vti_{tag}.hip"), "w") as f:
+        f.write(out)
+
+
 if __name__ == "__main__":
     fwd_file("float", F32_3D, F32_SWEEP_RADII, F32_3D_BIG_R)
     fwd_file("double", F64_3D, F64_SWEEP_RADII)
     adj_file("float", ADJ_F32_3D)
     adj_file("double", ADJ_F64_3D)
+    vti_file("float", VTI_F32)
+    vti_file("double", VTI_F64)

@@ -34,6 +34,9 @@ EXPORTS = [
     "fd_gradient_finish", "fd_batch_workspace_bytes", "fd_batch_create", "fd_batch_destroy",
     "fd_batch_set", "fd_batch_step", "fd_copy_probe", "fd_kernel_config", "fd_set_tuning",
     "fd_last_error",
+    "fd_vti_z_weights", "fd_vti_dt_max", "fd_vti_workspace_bytes", "fd_vti_create", "fd_vti_destroy",
+    "fd_vti_inject", "fd_vti_record", "fd_vti_step", "fd_vti_sync", "fd_vti_get_step", "fd_vti_get_state",
+    "fd_vti_set_state", "fd_vti_kernel_config", "fd_vti_set_tuning",
 ]
 
 
@@ -90,6 +93,23 @@ def lib():
             "fd_kernel_config": (ctypes.c_char_p, [P]),
             "fd_set_tuning": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
             "fd_last_error": (ctypes.c_char_p, []),
+            "fd_vti_z_weights": (ctypes.c_int, [ctypes.POINTER(D), I64, ctypes.c_int, ctypes.POINTER(D)]),
+            "fd_vti_dt_max": (D, [ctypes.c_int, ctypes.c_int, D, ctypes.POINTER(D), I64, D, D, D]),
+            "fd_vti_workspace_bytes": (ctypes.c_int, [pgrid, ctypes.c_int, ctypes.c_int, ctypes.c_int, I64, I64,
+                                                      ctypes.POINTER(SZ)]),
+            "fd_vti_create": (ctypes.c_int, [ctypes.POINTER(P), pgrid, ctypes.c_int, ctypes.c_int, D,
+                                             ctypes.POINTER(D), D, P, P, P, ctypes.c_int, P, SZ, I64, I64, P]),
+            "fd_vti_destroy": (ctypes.c_int, [P]),
+            "fd_vti_inject": (ctypes.c_int, [P, P, I64, ctypes.POINTER(I64), D, D]),
+            "fd_vti_record": (ctypes.c_int, [P, ctypes.POINTER(I32), I64, P, P, I64]),
+            "fd_vti_step": (ctypes.c_int, [P, I64]),
+            "fd_vti_sync": (ctypes.c_int, [P]),
+            "fd_vti_get_step": (ctypes.c_int, [P, ctypes.POINTER(I64)]),
+            "fd_vti_get_state": (ctypes.c_int, [P, P, P, P, P]),
+            "fd_vti_set_state": (ctypes.c_int, [P, P, P, P, P, I64]),
+            "fd_vti_kernel_config": (ctypes.c_char_p, [P]),
+            "fd_vti_set_tuning": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                                 ctypes.c_int]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -289,3 +309,101 @@ def fd_kernel_config(ctx: int) -> str:
 
 def fd_set_tuning(dtype, r: int, ndim: int, config: int, zchunk: int = 0):
     _check(lib().fd_set_tuning(dtype_code(dtype), r, ndim, config, zchunk), "fd_set_tuning")
+
+
+# ------------------------------------------------------------------ VTI propagator
+
+
+def _coords(zc):
+    """Host double array of plane coordinates (or None) and its ctypes pointer."""
+    import numpy as np
+
+    if zc is None:
+        return None, None
+    a = np.ascontiguousarray(np.asarray(zc, dtype=np.float64))
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def fd_vti_z_weights(zc, nz: int, rz: int):
+    import numpy as np
+
+    a, pa = _coords(zc)
+    out = np.zeros((nz, 2 * rz + 1), dtype=np.float64)
+    _check(lib().fd_vti_z_weights(pa, int(nz), int(rz), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+           "fd_vti_z_weights")
+    return out
+
+
+def fd_vti_dt_max(rxy: int, rz: int, h: float, zc, nz: int, vz_max: float, eps_max: float, delta_max: float) -> float:
+    a, pa = _coords(zc)
+    v = lib().fd_vti_dt_max(int(rxy), int(rz), float(h), pa, int(nz), float(vz_max), float(eps_max),
+                            float(delta_max))
+    if v < 0:
+        raise FdError(FD_E_INVAL, "fd_vti_dt_max", "bad arguments")
+    return v
+
+
+def fd_vti_workspace_bytes(shape, rxy: int, rz: int, dtype, max_sources: int, max_receivers: int) -> int:
+    out = ctypes.c_size_t()
+    _check(lib().fd_vti_workspace_bytes(ctypes.byref(make_grid(shape)), int(rxy), int(rz), dtype_code(dtype),
+                                        int(max_sources), int(max_receivers), ctypes.byref(out)),
+           "fd_vti_workspace_bytes")
+    return out.value
+
+
+def fd_vti_create(shape, rxy, rz, h, zc, dt, vz, eps, delta, dtype, workspace, max_sources, max_receivers,
+                  stream) -> int:
+    h_ = ctypes.c_void_p()
+    a, pa = _coords(zc)
+    _check(lib().fd_vti_create(ctypes.byref(h_), ctypes.byref(make_grid(shape)), int(rxy), int(rz), float(h), pa,
+                               float(dt), ptr(vz), ptr(eps), ptr(delta), dtype_code(dtype), ptr(workspace),
+                               workspace.numel(), int(max_sources), int(max_receivers), stream), "fd_vti_create")
+    return h_.value
+
+
+def fd_vti_destroy(ctx: int):
+    _check(lib().fd_vti_destroy(ctx), "fd_vti_destroy")
+
+
+def fd_vti_inject(ctx: int, wavelet, pos, amp_p: float = 1.0, amp_q: float = 0.0):
+    p = (ctypes.c_int64 * 3)(*pos)
+    _check(lib().fd_vti_inject(ctx, ptr(wavelet), wavelet.numel(), p, float(amp_p), float(amp_q)), "fd_vti_inject")
+
+
+def fd_vti_record(ctx: int, positions, traces_p, traces_q, cap: int):
+    import numpy as np
+
+    pos = np.ascontiguousarray(np.asarray(positions, dtype=np.int32).reshape(-1, 3))
+    _check(lib().fd_vti_record(ctx, pos.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), pos.shape[0],
+                               ptr(traces_p), ptr(traces_q), int(cap)), "fd_vti_record")
+
+
+def fd_vti_step(ctx: int, nsteps: int):
+    _check(lib().fd_vti_step(ctx, int(nsteps)), "fd_vti_step")
+
+
+def fd_vti_sync(ctx: int):
+    _check(lib().fd_vti_sync(ctx), "fd_vti_sync")
+
+
+def fd_vti_get_step(ctx: int) -> int:
+    s = ctypes.c_int64()
+    _check(lib().fd_vti_get_step(ctx, ctypes.byref(s)), "fd_vti_get_step")
+    return s.value
+
+
+def fd_vti_get_state(ctx: int, p=None, p_prev=None, q=None, q_prev=None):
+    _check(lib().fd_vti_get_state(ctx, ptr(p), ptr(p_prev), ptr(q), ptr(q_prev)), "fd_vti_get_state")
+
+
+def fd_vti_set_state(ctx: int, p, p_prev, q, q_prev, step: int):
+    _check(lib().fd_vti_set_state(ctx, ptr(p), ptr(p_prev), ptr(q), ptr(q_prev), int(step)), "fd_vti_set_state")
+
+
+def fd_vti_kernel_config(ctx: int) -> str:
+    return lib().fd_vti_kernel_config(ctx).decode()
+
+
+def fd_vti_set_tuning(dtype, rxy: int, rz: int, config: int, zchunk: int = 0):
+    _check(lib().fd_vti_set_tuning(dtype_code(dtype), int(rxy), int(rz), int(config), int(zchunk)),
+           "fd_vti_set_tuning")

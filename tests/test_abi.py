@@ -40,7 +40,7 @@ def test_exports_every_declared_symbol(F):
 
 
 def test_weights_match_oracle(F, oracle_mod):
-    for r in range(1, 9):
+    for r in range(1, 13):
         w = np.array(F.fd_weights(r))
         wo = oracle_mod.weights_f64(r)
         assert np.array_equal(w[1:], wo[1:])  # both correctly rounded from exact rationals
@@ -60,7 +60,7 @@ def test_invalid_arguments_rejected(F):
         F.fd_weights(0)
     assert e.value.status == F.FD_E_INVAL
     with pytest.raises(F.FdError):
-        F.fd_weights(9)
+        F.fd_weights(13)
     with pytest.raises(F.FdError):
         F.fd_dt_max(3, 4, -1.0, 1.0)
     for bad_shape, r in [((0, 4, 4), 4), ((4, 4, 4), 0), ((4, 4, 4), 9), ((5,), 2)]:
@@ -94,3 +94,50 @@ def test_tuning_table_accepts_known_configs(F):
     for cfg in range(7):
         F.fd_set_tuning("f32", 4, 3, cfg)
     F.fd_set_tuning("f32", 4, 3, 0)  # restore the default
+
+
+# ----------------------------------------------------------------------------- VTI host entry points
+
+
+def _stretched(nz, rz, dz, a=0.35):
+    k = np.arange(-rz, nz + rz, dtype=np.float64)
+    return np.round(dz * k * (1.0 + a * (k / nz) ** 2) * 64.0) / 64.0
+
+
+@pytest.mark.parametrize("rz", [1, 2, 4, 8])
+def test_vti_z_weights_match_oracle(F, oracle_mod, rz):
+    # library: Fornberg's recursion in FP64; oracle: exact moment equations over the rationals
+    for zc in (oracle_mod.uniform_z(12, rz, 10.0), _stretched(12, rz, 9.0)):
+        got = F.fd_vti_z_weights(zc, 12, rz)
+        ref = oracle_mod.z_weights(zc, rz)
+        scale = np.abs(ref).sum(axis=1, keepdims=True)
+        assert np.max(np.abs(got - ref) / scale) <= 1e-13
+
+
+def test_vti_dt_max_matches_oracle(F, oracle_mod):
+    for (rxy, rz, dz) in [(12, 8, 10.0), (4, 2, 7.0), (8, 4, 12.5)]:
+        zc = oracle_mod.uniform_z(10, rz, dz)
+        for (e, d) in [(0.0, 0.0), (0.25, 0.1), (0.2, 0.2)]:
+            a = F.fd_vti_dt_max(rxy, rz, 10.0, zc, 10, 3000.0, e, d)
+            b = oracle_mod.vti_dt_max(rxy, rz, 10.0, oracle_mod.z_weights(zc, rz), np.full((10, 2, 2), 3000.0), e, d)
+            assert abs(a - b) <= 1e-12 * b
+    # NULL coordinates mean a uniform spacing h
+    zc = oracle_mod.uniform_z(6, 4, 10.0)
+    assert F.fd_vti_dt_max(12, 4, 10.0, None, 6, 2500.0, 0.1, 0.05) == F.fd_vti_dt_max(12, 4, 10.0, zc, 6, 2500.0,
+                                                                                       0.1, 0.05)
+
+
+def test_vti_invalid_arguments_rejected(F):
+    with pytest.raises(F.FdError):
+        F.fd_vti_z_weights([0.0, 1.0, 1.0, 2.0, 3.0], 3, 1)          # not strictly increasing
+    with pytest.raises(F.FdError):
+        F.fd_vti_dt_max(6, 2, 10.0, None, 8, 2000.0, 0.1, 0.0)        # unsupported xy radius
+    with pytest.raises(F.FdError):
+        F.fd_vti_dt_max(4, 8, 10.0, None, 8, 2000.0, 0.1, 0.0)        # rz > rxy
+    with pytest.raises(F.FdError):
+        F.fd_vti_workspace_bytes((8, 8), 4, 2, "f32", 1, 0)            # 2-D grid
+    with pytest.raises(F.FdError) as e:
+        F.fd_vti_set_tuning("f32", 12, 8, 99)
+    assert e.value.status == F.FD_E_RANGE
+    ws = F.fd_vti_workspace_bytes((64, 64, 64), 12, 8, "f32", 1, 10)
+    assert ws >= 7 * 64 ** 3 * 4

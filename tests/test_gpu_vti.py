@@ -1,0 +1,252 @@
+"""GPU parity of the two-field VTI propagator (needs an MI355X).
+
+Against the FP64 oracle at sizes it finishes in seconds (several tiles, ragged
+edges, stretched z grids, several z chunks): FP32 <= 1e-4 and FP64 <= 1e-11
+relative L2 on p, q (both time levels) and the receiver traces.  At the full
+512^3 benchmark grid, in the launch configuration the benchmark times, sampled
+outputs are checked one by one: the oracle advances a box around each sample that
+contains the sample's whole domain of dependence."""
+
+import numpy as np
+import pytest
+
+import workloads
+from gpu_util import rel_l2, say
+
+pytestmark = pytest.mark.gpu
+
+
+def run_vti_gpu(vz, eps, delta, h, zc, dt, rxy, rz, T, dtype="f32", sources=(), receivers=None, state=None,
+                tuning=None, label=""):
+    """T steps of the VTI propagator through the C ABI.  sources: [(pos, samples, amp_p, amp_q)]."""
+    import torch
+
+    from paper_1410_1387_amd import fdwave as F
+    from paper_1410_1387_amd.vti import VtiPropagator
+
+    tdt = torch.float32 if dtype == "f32" else torch.float64
+    say(f"{label} vti shape={np.shape(vz)} rxy={rxy} rz={rz} T={T} {dtype} tuning={tuning}")
+    if tuning is not None:
+        F.fd_vti_set_tuning(dtype, rxy, rz, tuning[0], tuning[1])
+    try:
+        nrec = 0 if receivers is None else len(receivers)
+        g = lambda a: torch.tensor(np.asarray(a), dtype=tdt, device="cuda")
+        p = VtiPropagator(g(vz), g(eps), g(delta), rxy, rz, h, dt, zc=zc, dtype=dtype,
+                          max_sources=max(1, len(sources)), max_receivers=nrec)
+    finally:
+        if tuning is not None:
+            F.fd_vti_set_tuning(dtype, rxy, rz, 0, 0)
+    for pos, wav, ap, aq in sources:
+        p.inject(g(wav), pos, ap, aq)
+    trp = trq = None
+    if nrec:
+        trp, trq = p.record(receivers, T, record_q=True)
+    if state is not None:
+        p.set_state(*[g(a) for a in state], step=0)
+    p.step(T)
+    pn, pm, qn, qm = p.state()
+    out = {"p": pn, "p_prev": pm, "q": qn, "q_prev": qm, "traces_p": trp, "traces_q": trq}
+    out = {k: (v.double().cpu().numpy() if v is not None else None) for k, v in out.items()}
+    out["config"] = p.kernel_config
+    p.close()
+    return out
+
+
+def _model(shape, seed, eps_range=(0.05, 0.25)):
+    rng = np.random.default_rng(seed)
+    vz = workloads.layered_velocity(shape, seed=seed)
+    nz = shape[0]
+    e = rng.uniform(*eps_range, size=nz)
+    d = e * rng.uniform(0.2, 0.8, size=nz)
+    eps = np.ascontiguousarray(np.broadcast_to(e[:, None, None], shape))
+    delta = np.ascontiguousarray(np.broadcast_to(d[:, None, None], shape))
+    return vz, eps, delta
+
+
+def _compare(out, ref, tol, fields=("p", "p_prev", "q", "q_prev", "traces_p", "traces_q")):
+    errs = {}
+    for f in fields:
+        if out.get(f) is None:
+            continue
+        errs[f] = rel_l2(out[f], ref[f])
+    say(f"  {out['config']}: " + ", ".join(f"{k} {v:.2e}" for k, v in errs.items()))
+    for f, e in errs.items():
+        assert e <= tol, (f, e)
+
+
+CASES = [
+    # (shape (nz, ny, nx), rxy, rz, z grid, T)
+    ((40, 36, 70), 12, 8, "stretched", 60),
+    ((33, 20, 130), 4, 4, "uniform7", 80),
+    ((24, 18, 20), 8, 2, "stretched", 50),
+    ((5, 7, 9), 2, 1, "uniform10", 30),
+]
+
+
+@pytest.mark.parametrize("dtype,tol", [("f32", 1e-4), ("f64", 1e-11)])
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[0]}-r{c[1]}.{c[2]}-{c[3]}")
+def test_vti_vs_oracle(oracle_mod, case, dtype, tol):
+    shape, rxy, rz, zkind, T = case
+    nz, ny, nx = shape
+    h = 10.0
+    vz, eps, delta = _model(shape, seed=rxy * 10 + rz)
+    if zkind == "stretched":
+        zc = workloads.stretched_z(nz, rz, h, 1.5)
+    else:
+        zc = oracle_mod.uniform_z(nz, rz, float(zkind[len("uniform"):]))
+    dt = 0.6 * oracle_mod.vti_dt_max(rxy, rz, h, oracle_mod.z_weights(zc, rz), vz, eps, delta)
+    wav = oracle_mod.ricker(T, dt, 40.0, 0.025)
+    src = [((nx // 2, ny // 3, nz // 2), wav, 1.0, 0.0), ((1, ny - 2, 1), 0.5 * wav, 0.3, 0.7)]
+    rec = np.array([(x, y, z) for z in (0, nz // 2, nz - 1) for y in (0, ny // 2, ny - 1)
+                    for x in range(0, nx, max(1, nx // 9))])
+    ref = oracle_mod.vti_forward(vz, eps, delta, h, dt, rxy, rz, T, zc=zc, sources=src, receivers=rec)
+    out = run_vti_gpu(vz, eps, delta, h, zc, dt, rxy, rz, T, dtype, sources=src, receivers=rec)
+    _compare(out, ref, tol)
+
+
+def test_vti_chunking_and_tiles_bitwise(oracle_mod):
+    # z chunks and tile shapes change which workgroup computes a point, never its arithmetic
+    shape = (70, 24, 40)
+    rxy, rz, h = 12, 8, 10.0
+    vz, eps, delta = _model(shape, seed=3)
+    zc = workloads.stretched_z(shape[0], rz, h)
+    dt = 0.5 * oracle_mod.vti_dt_max(rxy, rz, h, oracle_mod.z_weights(zc, rz), vz, eps, delta)
+    T = 40
+    wav = oracle_mod.ricker(T, dt, 40.0, 0.025)
+    src = [((20, 12, 30), wav, 1.0, 0.0)]
+    outs = [run_vti_gpu(vz, eps, delta, h, zc, dt, rxy, rz, T, "f32", sources=src, tuning=t, label=str(t))
+            for t in [None, (0, 9), (1, 16), (2, 70), (3, 23)]]
+    for o in outs[1:]:
+        for f in ("p", "p_prev", "q", "q_prev"):
+            assert np.array_equal(o[f], outs[0][f]), (o["config"], f)
+    ref = oracle_mod.vti_forward(vz, eps, delta, h, dt, rxy, rz, T, zc=zc, sources=src)
+    _compare(outs[0], ref, 1e-4, ("p", "q"))
+
+
+def test_vti_isotropic_limit(oracle_mod):
+    # eps = delta = 0, equal radii, dz = h, the source in both fields: p = q bitwise (the two
+    # updates then do the same operations on the same values) and both equal the acoustic
+    # oracle's u
+    shape = (21, 26, 33)
+    r, h = 4, 10.0
+    vz = workloads.layered_velocity(shape, seed=11)
+    zero = np.zeros(shape)
+    dt = 0.6 * oracle_mod.dt_max(3, r, h, vz.max())
+    T = 70
+    wav = oracle_mod.ricker(T, dt, 35.0, 0.03)
+    src = (16, 13, 10)
+    out = run_vti_gpu(vz, zero, zero, h, None, dt, r, r, T, "f32", sources=[(src, wav, 1.0, 1.0)])
+    assert np.array_equal(out["p"], out["q"])
+    ref = oracle_mod.forward(vz, h, dt, r, T, [(src, wav)])
+    assert rel_l2(out["p"], ref["u"]) <= 1e-4
+
+
+def test_vti_state_round_trip(oracle_mod):
+    # arbitrary initial p, q at both levels: every point of the grid carries signal
+    shape = (26, 30, 45)
+    rxy, rz, h = 12, 4, 10.0
+    vz, eps, delta = _model(shape, seed=21)
+    zc = workloads.stretched_z(shape[0], rz, h, 1.3)
+    dt = 0.5 * oracle_mod.vti_dt_max(rxy, rz, h, oracle_mod.z_weights(zc, rz), vz, eps, delta)
+    rng = np.random.default_rng(4)
+    smooth = [workloads.gaussian_smooth_periodic(rng.standard_normal(shape), 2.0) for _ in range(4)]
+    T = 25
+    ref = oracle_mod.vti_forward(vz, eps, delta, h, dt, rxy, rz, T, zc=zc, state=smooth)
+    for dtype, tol in (("f32", 1e-4), ("f64", 1e-11)):
+        out = run_vti_gpu(vz, eps, delta, h, zc, dt, rxy, rz, T, dtype, state=smooth)
+        _compare(out, ref, tol, ("p", "p_prev", "q", "q_prev"))
+
+
+def test_vti_errors(oracle_mod):
+    import torch
+
+    from paper_1410_1387_amd import fdwave as F
+    from paper_1410_1387_amd.vti import VtiPropagator
+
+    shape = (12, 10, 14)
+    vz = torch.full(shape, 2000.0, device="cuda")
+    dt_ok = 0.5 * VtiPropagator.dt_max(8, 4, 10.0, shape[0], 2000.0, 0.2, 0.1)
+
+    def make(**kw):
+        a = dict(vz=vz, eps=0.2, delta=0.1, rxy=8, rz=4, h=10.0, dt=dt_ok, max_sources=1, max_receivers=2)
+        a.update(kw)
+        return VtiPropagator(**a)
+
+    cases = [
+        (dict(delta=0.3), F.FD_E_UNSTABLE),                     # delta > eps: growing mode
+        (dict(dt=3.0 * dt_ok), F.FD_E_UNSTABLE),                # above the stability limit
+        (dict(rxy=6), F.FD_E_INVAL),                            # no kernel for this radius
+        (dict(vz=torch.zeros(shape, device="cuda")), F.FD_E_INVAL),
+        (dict(zc=np.zeros(shape[0] + 8)), F.FD_E_INVAL),        # coordinates not increasing
+    ]
+    for kw, status in cases:
+        say(f"expect {F.STATUS_NAMES[status]} for {list(kw)}")
+        with pytest.raises(F.FdError) as e:
+            make(**kw)
+        assert e.value.status == status, kw
+    p = make()
+    w = p.ricker(10)
+    with pytest.raises(F.FdError) as e:
+        p.inject(w, (14, 0, 0))
+    assert e.value.status == F.FD_E_RANGE
+    p.record([(1, 1, 1), (2, 2, 2)], 5)
+    with pytest.raises(F.FdError) as e:
+        p.step(6)                                               # trace capacity 5
+    assert e.value.status == F.FD_E_RANGE
+    p.step(5)
+    p.sync()
+    p.close()
+
+
+# ----------------------------------------------------------------------------- full-size workload
+
+
+def test_vti_full_grid_sampled(oracle_mod):
+    """512^3, rxy = 12, rz = 8, FP32, stretched z, layered VTI model (the benchmark's
+    workload and launch configuration), started from a random state plus the Ricker
+    source.  After T steps a point depends only on the box of half-width T rxy (xy)
+    and T rz (z) around it, so the oracle advances that box alone (zero outside, which
+    is exact at the true boundary and reaches no sample from the artificial faces)."""
+    import torch
+
+    from paper_1410_1387_amd.vti import VtiPropagator
+
+    shot = workloads.VtiShot()
+    n, rxy, rz, h = shot.n, shot.rxy, shot.rz, shot.h
+    vz, eps, delta = shot.models(np.float32)
+    zc = shot.zc()
+    dt = shot.courant * VtiPropagator.dt_max(rxy, rz, h, n, float(vz.max()), float(eps.max()), float(delta.max()),
+                                             zc=zc)
+    T = 3
+    rng = np.random.default_rng(77)
+    state = [rng.uniform(-1.0, 1.0, size=shot.shape).astype(np.float32) for _ in range(4)]
+    wav = oracle_mod.ricker(T, dt, shot.f0, 0.0)  # nonzero from the first step
+    say("512^3 VTI: upload and 3 steps")
+    g = lambda a: torch.from_numpy(a).cuda()
+    p = VtiPropagator(g(vz), g(eps), g(delta), rxy, rz, h, dt, zc=zc, dtype="f32")
+    p.inject(torch.tensor(wav, dtype=torch.float32, device="cuda"), shot.source, 1.0, 0.0)
+    p.set_state(*[g(a) for a in state], step=0)
+    p.step(T)
+    got = [a.cpu().numpy() for a in p.state()]
+    say(f"  {p.kernel_config}")
+    p.close()
+    mxy, mz = T * rxy + 3, T * rz + 3
+    samples = [(0, 0, 0), (n - 1, n - 1, n - 1), (0, n - 1, n // 2), (n // 2, 0, n - 1), shot.source,
+               (137, 401, 290), (511, 200, 3), (64, 65, 448)]
+    for (sx, sy, sz) in samples:
+        x0, x1 = max(0, sx - mxy), min(n, sx + mxy + 1)
+        y0, y1 = max(0, sy - mxy), min(n, sy + mxy + 1)
+        z0, z1 = max(0, sz - mz), min(n, sz + mz + 1)
+        box = (slice(z0, z1), slice(y0, y1), slice(x0, x1))
+        sub = [a[box].astype(np.float64) for a in state]
+        src = []
+        if all(lo <= c < hi for c, lo, hi in zip(shot.source, (x0, y0, z0), (x1, y1, z1))):
+            src = [((shot.source[0] - x0, shot.source[1] - y0, shot.source[2] - z0), wav, 1.0, 0.0)]
+        ref = oracle_mod.vti_forward(vz[box], eps[box], delta[box], h, dt, rxy, rz, T, zc=zc[z0: z1 + 2 * rz],
+                                     sources=src, state=sub)
+        c = (slice(max(0, sz - 2 - z0), sz + 3 - z0), slice(max(0, sy - 2 - y0), sy + 3 - y0),
+             slice(max(0, sx - 2 - x0), sx + 3 - x0))
+        for i, f in enumerate(("p", "p_prev", "q", "q_prev")):
+            e = rel_l2(got[i][box][c], ref[f][c])
+            assert e <= 1e-5, ((sx, sy, sz), f, e)
+        say(f"  sample {(sx, sy, sz)} ok")

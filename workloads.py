@@ -210,6 +210,64 @@ class GradientCase:
         return rng.integers(lo, hi, size=(self.fd_cells, 3))  # (z, y, x) array indices
 
 
+def stretched_z(nz: int, rz: int, h: float, stretch: float = 1.5) -> np.ndarray:
+    """Coordinates of planes -rz .. nz+rz-1 of a z grid whose spacing grows linearly with
+    depth from h (top) to stretch * h (bottom), rounded to multiples of 1/64 m.  The rz
+    ghost planes above and below continue the end spacings."""
+    k = np.arange(-rz, nz + rz - 1, dtype=np.float64)
+    frac = np.clip(k, 0, max(nz - 1, 1)) / max(nz - 1, 1)
+    dz = h * (1.0 + (stretch - 1.0) * frac)
+    z = np.concatenate([[-rz * h], -rz * h + np.cumsum(dz)])
+    return np.round(z * 64.0) / 64.0
+
+
+@dataclasses.dataclass
+class VtiShot:
+    """One shot of the two-field VTI propagator: layered vertical velocity with layered
+    anisotropy (eps ~ U[0.05, 0.25] per layer, delta = eps * U[0.2, 0.8], so delta <= eps),
+    a z grid stretched with depth, Ricker source forcing p only (the form of eq. (p))."""
+
+    n: int = 512
+    rxy: int = 12
+    rz: int = 8
+    dtype: str = "f32"
+    nsteps: int = 1000
+    h: float = 10.0
+    stretch: float = 1.5
+    courant: float = 0.5
+    f0: float = 15.0
+    seed: int = 5
+
+    @property
+    def shape(self):
+        return (self.n, self.n, self.n)
+
+    def models(self, dtype=np.float64):
+        s_v, s_e, s_d = spawn_seeds(self.seed, 3)
+        nl = 8
+        vz = layered_velocity(self.shape, nl, seed=s_v, dtype=dtype)
+        e = np.random.default_rng(s_e).uniform(0.05, 0.25, size=nl)
+        d = e * np.random.default_rng(s_d).uniform(0.2, 0.8, size=nl)
+        layer = np.minimum((np.arange(self.n) * nl) // self.n, nl - 1)
+        eps = np.ascontiguousarray(np.broadcast_to(e[layer][:, None, None], self.shape), dtype=dtype)
+        delta = np.ascontiguousarray(np.broadcast_to(d[layer][:, None, None], self.shape), dtype=dtype)
+        return vz, eps, delta
+
+    def zc(self) -> np.ndarray:
+        return stretched_z(self.n, self.rz, self.h, self.stretch)
+
+    @property
+    def source(self):
+        return (self.n // 2, self.n // 2, max(1, round(16 * self.n / 512)))
+
+    def receivers(self):
+        return surface_receivers(self.n, self.n, self.source[2], 4)
+
+    @property
+    def npoints(self) -> int:
+        return self.n ** 3
+
+
 @dataclasses.dataclass
 class ServeRequest:
     rid: int
