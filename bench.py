@@ -10,8 +10,11 @@ A shot runs every row of the forward path on the GPU: model preparation
 stencil launches with the source and receivers fused in.  The velocity model is
 resident in HBM before the timed region starts.
 
-    python bench.py [--steps K] [--warmup W] [--no-cpu] [--gradient] [--serving] [--copy-probe]
+    python bench.py [--steps K] [--warmup W] [--no-cpu] [--no-vti] [--gradient] [--serving] [--copy-probe]
     python bench.py --summarize-prof DIR     # rocprofv3 CSVs -> profiles/ summary
+
+The JSON line also carries the paper's own benchmark kernel, the two-field VTI
+propagator (R_xy = 12, R_z = 8) on a 512^3 FP32 grid, under "vti".
 
 Prints one JSON line.
 """
@@ -32,25 +35,31 @@ HBM_PEAK_GBS = 8000.0
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "fwd_r4_512_traffic.json")
 KERNEL_SOURCES = ["paper_1410_1387_amd/csrc/fd_stencil.h", "paper_1410_1387_amd/csrc/fd_fwd_f32.hip",
                   "paper_1410_1387_amd/csrc/fd_types.h"]
+VTI_PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "vti_r12_8_512_traffic.json")
+VTI_KERNEL_SOURCES = ["paper_1410_1387_amd/csrc/fd_stencil.h", "paper_1410_1387_amd/csrc/fd_vti.h",
+                      "paper_1410_1387_amd/csrc/fd_vti_f32.hip", "paper_1410_1387_amd/csrc/fd_types.h"]
+# the paper's best VTI rates (Mpts/s, FP32, R_xy = 12, R_z = 8), quoted as context only
+PAPER_VTI_MPTS = {"K20x, OCCA:OpenCL, 2 pts/thread": 2525.0, "K10 (one chip), OCCA:CUDA, 2 pts/thread": 1579.0,
+                  "2x Xeon (16 threads), OCCA:OpenMP": 1548.0}
 
 
-def kernel_hash() -> str:
+def kernel_hash(sources=KERNEL_SOURCES) -> str:
     h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
+    for p in sources:
         with open(os.path.join(ROOT, p), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken
-    on the kernel source that is built now; otherwise None."""
+def measured_traffic(path=PROFILE_TRAFFIC, sources=KERNEL_SOURCES):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, if it was taken on
+    the kernel source that is built now; otherwise None."""
     try:
-        with open(PROFILE_TRAFFIC) as f:
+        with open(path) as f:
             d = json.load(f)
     except (OSError, ValueError):
         return None
-    if d.get("kernel_hash") != kernel_hash():
+    if d.get("kernel_hash") != kernel_hash(sources):
         return None
     return d.get("hbm_bytes_per_launch")
 
@@ -135,6 +144,77 @@ def run_forward(args):
     }
 
 
+def run_vti(args):
+    """The paper's own benchmark kernel: the two-field VTI propagator with R_xy = 12 and
+    R_z = 8 (Sec. 1), here on a 512^3 FP32 grid with a z spacing stretched from 10 m to
+    15 m with depth, layered vz / eps / delta (delta <= eps), Ricker 15 Hz forcing p at
+    (256, 256, 16), 1000 steps, 128 x 128 receivers recording p.  The model is resident
+    in HBM before the timed region."""
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_1410_1387_amd import fdwave as F
+
+    shot = workloads.VtiShot()
+    T, pts = shot.nsteps, shot.npoints
+    vz, eps, delta = (torch.from_numpy(a).cuda() for a in shot.models(np.float32))
+    zc = shot.zc()
+    dt = shot.courant * F.fd_vti_dt_max(shot.rxy, shot.rz, shot.h, zc, shot.n, float(vz.max()), float(eps.max()),
+                                        float(delta.max()))
+    rec = shot.receivers()
+    ws = torch.empty(F.fd_vti_workspace_bytes(shot.shape, shot.rxy, shot.rz, "f32", 1, len(rec)), dtype=torch.uint8,
+                     device="cuda")
+    wav = torch.empty(T, dtype=torch.float32, device="cuda")
+    traces = torch.empty((T, len(rec)), dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+    sp = F.stream_ptr(stream)
+
+    def one_shot(ev=None):
+        ctx = F.fd_vti_create(shot.shape, shot.rxy, shot.rz, shot.h, zc, dt, vz, eps, delta, "f32", ws, 1, len(rec),
+                              sp)
+        F.fd_ricker(wav, dt, shot.f0, 1.5 / shot.f0, sp)
+        F.fd_vti_inject(ctx, wav, shot.source, 1.0, 0.0)
+        F.fd_vti_record(ctx, rec, traces, None, T)
+        if ev is not None:
+            ev[0].record(stream)
+        F.fd_vti_step(ctx, T)
+        if ev is not None:
+            ev[1].record(stream)
+        F.fd_vti_sync(ctx)
+        cfg = F.fd_vti_kernel_config(ctx)
+        F.fd_vti_destroy(ctx)
+        return cfg
+
+    one_shot()
+    torch.cuda.synchronize()
+    nshots = max(1, min(args.steps, 2))
+    events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(nshots)]
+    t0 = time.perf_counter()
+    for k in range(nshots):
+        cfg = one_shot(events[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    launch_ms = sum(a.elapsed_time(b) for a, b in events) / (nshots * T)
+    algo = 36.0 * pts  # read p, q at n and n-1 and ax, an, az; write p, q at n+1 (FP32)
+    achieved = algo / (launch_ms * 1e-3) / 1e9
+    rate = pts / (launch_ms * 1e-3) / 1e9
+    tr = measured_traffic(VTI_PROFILE_TRAFFIC, VTI_KERNEL_SOURCES)
+    log(f"vti: stencil {launch_ms * 1e3:.1f} us/launch = {rate:.1f} Gpts/s, {achieved:.0f} GB/s algorithmic ({cfg})")
+    return {
+        "workload": "vti_512_rxy12_rz8_stretched_z_fp32", "gpts_per_s_per_shot": round(pts * T * nshots / wall / 1e9, 2),
+        "stencil_gpts_per_s": round(rate, 2), "launch_us": round(launch_ms * 1e3, 2),
+        "grid": list(shot.shape[::-1]), "rxy": shot.rxy, "rz": shot.rz, "time_steps_per_shot": T,
+        "z_spacing_m": [10.0, 15.0], "kernel": cfg,
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None if tr is None else round(tr / (launch_ms * 1e-3) / 1e9, 1),
+                     "algorithmic_bytes_per_launch": algo},
+        "paper_context_mpts": PAPER_VTI_MPTS,
+        "ratio_to_paper_best_gpu": round(rate * 1e3 / PAPER_VTI_MPTS["K20x, OCCA:OpenCL, 2 pts/thread"], 1),
+    }
+
+
 def run_copy_probe(nbytes=1 << 30, reps=3):
     """A plain device copy of known size: the reference that hardware byte counters are
     scaled by (what FETCH_SIZE / WRITE_SIZE report for exactly nbytes read and written)."""
@@ -173,31 +253,36 @@ def summarize_prof(d: str, out_json: str = PROFILE_TRAFFIC):
     fetch = counter("fetch/*counter_collection.csv", "FETCH_SIZE")
     write = counter("write/*counter_collection.csv", "WRITE_SIZE")
     copy = [k for k in fetch if "copy_probe" in k][0]
-    fwd = max((k for k in fetch if "fwd_kernel" in k), key=lambda k: fetch[k])
     probe_bytes = 1 << 30
     f_scale = probe_bytes / (fetch[copy] * 1024.0)
     w_scale = probe_bytes / (write[copy] * 1024.0)
     stats = {r["Name"]: r for r in rows("trace/*kernel_stats.csv")}
-    avg_ns = float(stats[fwd]["AverageNs"]) if fwd in stats else None
-    fb, wb = fetch[fwd] * 1024.0 * f_scale, write[fwd] * 1024.0 * w_scale
-    res = {
-        "kernel": fwd, "kernel_hash": kernel_hash(),
-        "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb, "hbm_bytes_per_launch": fb + wb,
-        "algorithmic_bytes_per_launch": 16.0 * 512 ** 3,
-        "fetch_scale": f_scale, "write_scale": w_scale, "copy_probe_bytes": probe_bytes,
-        "trace_avg_launch_ns": avg_ns,
-        "commands": [
-            "rocprofv3 --kernel-trace --stats -d DIR/trace -o trace --output-format csv -- "
-            "python3 bench.py --steps 1 --warmup 0 --no-cpu --copy-probe",
-            "rocprofv3 --pmc FETCH_SIZE -d DIR/fetch -o fetch --output-format csv -- "
-            "python3 bench.py --steps 1 --warmup 0 --no-cpu --copy-probe",
-            "rocprofv3 --pmc WRITE_SIZE -d DIR/write -o write --output-format csv -- "
-            "python3 bench.py --steps 1 --warmup 0 --no-cpu --copy-probe",
-        ],
-    }
-    with open(out_json, "w") as fh:
-        json.dump(res, fh, indent=1)
-    print(json.dumps(res, indent=1))
+    cmds = [
+        "rocprofv3 --kernel-trace --stats -d DIR/trace -o trace --output-format csv -- "
+        "python3 bench.py --steps 1 --warmup 0 --no-cpu --copy-probe",
+        "rocprofv3 --pmc FETCH_SIZE -d DIR/fetch -o fetch --output-format csv -- "
+        "python3 bench.py --steps 1 --warmup 0 --no-cpu --copy-probe",
+        "rocprofv3 --pmc WRITE_SIZE -d DIR/write -o write --output-format csv -- "
+        "python3 bench.py --steps 1 --warmup 0 --no-cpu --copy-probe",
+    ]
+    for tag, out_path, sources, algo in (("fwd_kernel", out_json, KERNEL_SOURCES, 16.0 * 512 ** 3),
+                                         ("vti_kernel", VTI_PROFILE_TRAFFIC, VTI_KERNEL_SOURCES, 36.0 * 512 ** 3)):
+        cands = [k for k in fetch if tag in k]
+        if not cands:
+            continue
+        kern = max(cands, key=lambda k: fetch[k])
+        avg_ns = float(stats[kern]["AverageNs"]) if kern in stats else None
+        fb, wb = fetch[kern] * 1024.0 * f_scale, write[kern] * 1024.0 * w_scale
+        res = {
+            "kernel": kern, "kernel_hash": kernel_hash(sources),
+            "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb, "hbm_bytes_per_launch": fb + wb,
+            "algorithmic_bytes_per_launch": algo,
+            "fetch_scale": f_scale, "write_scale": w_scale, "copy_probe_bytes": probe_bytes,
+            "trace_avg_launch_ns": avg_ns, "commands": cmds,
+        }
+        with open(out_path, "w") as fh:
+            json.dump(res, fh, indent=1)
+        print(json.dumps(res, indent=1))
 
 
 # --------------------------------------------------------------------------- CPU baseline
@@ -355,6 +440,7 @@ def main():
     ap.add_argument("--gradient", action="store_true", help="also time the adjoint gradient workload")
     ap.add_argument("--serving", action="store_true", help="also run the shot-serving workload")
     ap.add_argument("--copy-probe", action="store_true", help="run a 1 GiB copy (counter scaling reference)")
+    ap.add_argument("--no-vti", action="store_true", help="skip the VTI propagator section")
     ap.add_argument("--summarize-prof", metavar="DIR", help="summarize rocprofv3 CSV output and exit")
     args = ap.parse_args()
     if args.summarize_prof:
@@ -394,6 +480,8 @@ def main():
         "config": fw["config"],
         "roofline": fw["roofline"],
     }
+    if not args.no_vti:
+        out["vti"] = run_vti(args)
     if args.gradient:
         out["gradient"] = run_gradient()
     if args.serving:
