@@ -413,7 +413,8 @@ def run_serving(nreq=256, budget_gib=96, sequential=True):
     wall = time.perf_counter() - t0
     st = summarize(res)
     st.update({"wall_s": round(wall, 2), "budget_gib": budget_gib, "chunk_steps": 32,
-               "max_resident_shots": srv.stats["max_resident_shots"],
+               "max_resident_shots": srv.stats["max_resident_shots"], "fill_points": srv.fill_points,
+               "max_stepping_shots": srv.stats["max_stepping_shots"],
                "max_resident_gib": round(srv.stats["max_resident_bytes"] / 2 ** 30, 2),
                "batched_chunks": srv.stats["chunks"], "membership_changes": srv.stats["membership_changes"],
                "gpu_busy_s": round(srv.stats["gpu_busy_s"], 2), "host_admission_s": round(srv.stats["admit_s"], 2),

@@ -7,11 +7,16 @@
   (workspace + traces + wavelet) fits the budget and a batch slot is free; a shot's
   context is created on a separate setup stream, so admission overlaps with the
   batched work already on the GPU;
-* all admitted shots -- different grid sizes, same radius and dtype -- advance
-  together in one stencil launch per time step (``fd_batch_step``): every workgroup
-  finds its (shot, tile) in a prefix table and every shot keeps its step counter in
-  device memory, so a chunk of an even number of steps is a captured HIP graph that
-  is replayed while shots come and go;
+* the admitted shots -- different grid sizes, same radius and dtype -- that make up
+  the stepping window advance together in one stencil launch per time step
+  (``fd_batch_step``): every workgroup finds its (shot, tile) in a prefix table and
+  every shot keeps its step counter in device memory, so a chunk of an even number
+  of steps is a captured HIP graph that is replayed while shots come and go;
+* the window is the oldest admitted shots, taken in admission order until their grid
+  points per step reach ``fill_points``: enough work to fill the GPU (a small shot
+  alone leaves most compute units idle), but no more, so that shots finish in
+  roughly arrival order instead of all sharing the GPU at once (which would stretch
+  every shot's latency without raising throughput);
 * after each chunk the loop retires shots whose counters reached their step count,
   frees their memory and admits new ones at the next chunk boundary.
 
@@ -139,14 +144,17 @@ class ShotServer:
     """Persistent continuous-batching server for same-radius, same-dtype shots.
 
     budget_bytes  HBM the resident shots may hold together
-    max_shots     batch slots (shots advanced by one launch)
+    max_shots     resident shots (and batch slots)
     chunk         time steps per batched launch sequence (even: replayed as a graph)
+    fill_points   grid points per step the stepping window aims for (None: every
+                  resident shot steps)
     """
 
     def __init__(self, r: int = 4, dtype: str = "f32", budget_bytes: int = 64 << 30, max_shots: int = 64,
-                 chunk: int = 32, device: str = "cuda"):
+                 chunk: int = 32, device: str = "cuda", fill_points: Optional[int] = 320_000_000):
         self.r, self.dtype = r, dtype
         self.budget, self.max_shots, self.chunk = int(budget_bytes), int(max_shots), int(chunk)
+        self.fill_points = None if fill_points is None else int(fill_points)
         self.device = torch.device(device)
         if self.device.index is None:  # the worker thread needs an explicit device index
             self.device = torch.device(self.device.type, torch.cuda.current_device())
@@ -157,7 +165,8 @@ class ShotServer:
         self._stop = threading.Event()
         self.t0 = time.perf_counter()
         self.stats = {"chunks": 0, "membership_changes": 0, "max_resident_bytes": 0, "max_resident_shots": 0,
-                      "gpu_points": 0, "gpu_busy_s": 0.0, "chunk_points": 0, "admit_s": 0.0}
+                      "max_stepping_shots": 0, "gpu_points": 0, "gpu_busy_s": 0.0, "chunk_points": 0,
+                      "admit_s": 0.0}
         self._error: Optional[BaseException] = None
 
     # ------------------------------------------------------------------ public API
@@ -236,7 +245,8 @@ class ShotServer:
         bws = torch.empty(F.fd_batch_workspace_bytes(self.max_shots), dtype=torch.uint8, device=self.device)
         batch = F.fd_batch_create(self.max_shots, bws, F.stream_ptr(bstream))
         pending: collections.deque = collections.deque()
-        active: list = []
+        active: list = []      # resident shots, in admission order
+        stepping: list = []    # the window the batch advances
         used = 0
         dirty = False
         inflight: collections.deque = collections.deque()   # (event, [shots finishing in that chunk])
@@ -289,29 +299,33 @@ class ShotServer:
                 if not active and not inflight:
                     continue
                 if dirty:
-                    # fd_batch_set waits for the in-flight chunks before rewriting the table
-                    self._retire_done(inflight, wait_all=True)
-                    keep = [s for s in active if not s.future.done()]
-                    for s in active:
-                        if s.future.done():
-                            used -= s.footprint
-                            F.fd_destroy(s.ctx)
-                            s.tensors = None
-                    active = keep
-                    F.fd_batch_set(batch, [s.ctx for s in active], [s.req.nsteps for s in active])
-                    self.stats["membership_changes"] += 1
+                    want = self._window(active)
+                    if [id(s) for s in want] != [id(s) for s in stepping] or any(s.future.done() for s in active):
+                        # fd_batch_set waits for the in-flight chunks before rewriting the table
+                        self._retire_done(inflight, wait_all=True)
+                        keep = [s for s in active if not s.future.done()]
+                        for s in active:
+                            if s.future.done():
+                                used -= s.footprint
+                                F.fd_destroy(s.ctx)
+                                s.tensors = None
+                        active = keep
+                        stepping = self._window(active)
+                        F.fd_batch_set(batch, [s.ctx for s in stepping], [s.req.nsteps for s in stepping])
+                        self.stats["membership_changes"] += 1
+                        self.stats["max_stepping_shots"] = max(self.stats["max_stepping_shots"], len(stepping))
                     dirty = False
-                    if not active:
+                    if not stepping:
                         continue
-                before = {id(s): F.fd_get_step(s.ctx) for s in active}
+                before = {id(s): F.fd_get_step(s.ctx) for s in stepping}
                 ev0 = torch.cuda.Event(enable_timing=True)
                 ev0.record(bstream)
                 F.fd_batch_step(batch, self.chunk)
                 ev = torch.cuda.Event(enable_timing=True)
                 ev.record(bstream)
                 pts = sum((F.fd_get_step(s.ctx) - before[id(s)]) * (s.npoints // max(1, s.req.nsteps))
-                          for s in active)
-                finishing = [s for s in active if F.fd_get_step(s.ctx) >= s.req.nsteps and not s.future.done()
+                          for s in stepping)
+                finishing = [s for s in stepping if F.fd_get_step(s.ctx) >= s.req.nsteps and not s.future.done()
                              and not getattr(s, "_queued_done", False)]
                 for s in finishing:
                     s._queued_done = True
@@ -328,6 +342,20 @@ class ShotServer:
                     s.future.set_exception(RuntimeError("server stopped"))
                 F.fd_destroy(s.ctx)
             F.fd_batch_destroy(batch)
+
+    def _window(self, active: list) -> list:
+        """The oldest unfinished resident shots, in admission order, until their grid points
+        per step reach fill_points (at least one shot)."""
+        live = [s for s in active if not s.future.done() and not getattr(s, "_queued_done", False)]
+        if self.fill_points is None:
+            return live
+        out, pts = [], 0
+        for s in live:
+            if out and pts >= self.fill_points:
+                break
+            out.append(s)
+            pts += s.npoints // max(1, s.req.nsteps)
+        return out
 
     def _retire_done(self, inflight, wait_all: bool) -> bool:
         """Complete the shots of finished chunks (all in-flight chunks when wait_all, else all

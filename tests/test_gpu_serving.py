@@ -113,7 +113,7 @@ def test_server_alone_vs_mix_bitwise(oracle_mod):
     st = summarize(list(res.values()))
     say(f"served {st['completed']} p50 {st['p50_latency_s']:.3f}s p99 {st['p99_latency_s']:.3f}s; {srv.stats}")
     assert st["completed"] == len(reqs)
-    assert srv.stats["max_resident_shots"] > 1  # shots really shared launches
+    assert srv.stats["max_stepping_shots"] > 1  # shots really shared launches
     for rid, r in res.items():
         assert r.status == "ok" and seq[rid].status == "ok"
         assert np.array_equal(r.traces.cpu().numpy(), seq[rid].traces.cpu().numpy()), rid
