@@ -30,6 +30,9 @@ Finite-differences on multi-threaded architectures using OCCA") defines it:
   scheme, the symmetric radius-Rxy xy stencil acting on p, and a per-plane
   2Rz+1-point z stencil acting on q whose weights absorb a variable spacing
   dz_k (Sec. 1).  ``vti_oracle.c`` holds the loops.
+* ``cerjan``, ``damping_field`` -- the absorbing sponge the paper embeds the domain in
+  (Sec. 1, after Cerjan et al., whose profile and constants the paper does not print):
+  ``forward(..., damping=...)`` scales both time levels by G every step.
 * ``gradient``  -- the discrete adjoint (Lagrange multiplier recursion of the
   forward scheme) of J = 1/2 sum (traces - observed)^2 with respect to v.
   Not in the paper; its statement of the problem names full waveform inversion
@@ -68,6 +71,8 @@ __all__ = [
     "z_weights",
     "vti_dt_max",
     "vti_forward",
+    "cerjan",
+    "damping_field",
 ]
 
 
@@ -103,7 +108,7 @@ def _lib():
         lib.fdo_laplacian.argtypes = [ctypes.c_int, P, ctypes.c_int, P, ctypes.c_double, ctypes.c_int, P, P]
         lib.fdo_forward.argtypes = [
             ctypes.c_int, P, ctypes.c_int, P, ctypes.c_double, ctypes.c_double, P, ctypes.c_int,
-            I64, I64, P, P, I64, P, P, P, P, P,
+            I64, I64, P, P, I64, P, P, P, P, P, P,
         ]
         lib.fdo_adjoint.argtypes = [
             ctypes.c_int, P, ctypes.c_int, P, ctypes.c_double, ctypes.c_double, P, ctypes.c_int,
@@ -259,8 +264,37 @@ def _source_arrays(shape, sources, nsteps):
     return idx, np.ascontiguousarray(samples)
 
 
+def cerjan(n: int, width: int, alpha: float, lo: bool = True, hi: bool = True) -> np.ndarray:
+    """Cerjan et al. (Geophysics 50, 1985) sponge factor along one axis of n points: in a
+    strip of `width` points at a damped face, the point at distance i from the face
+    (i = 0 outermost) gets exp(-(alpha (width - i))^2); 1 elsewhere (factors of two
+    overlapping strips multiply)."""
+    g = np.ones(n)
+    for i in range(min(width, n)):
+        f = math.exp(-(alpha * (width - i)) ** 2)
+        if lo:
+            g[i] *= f
+        if hi:
+            g[n - 1 - i] *= f
+    return g
+
+
+def damping_field(shape, width: int, alpha: float, faces=(True,) * 6) -> np.ndarray:
+    """Point-wise sponge factor G of a dense (nz, ny, nx) / (ny, nx) grid: the product of
+    the per-axis Cerjan profiles; faces = (x-, x+, y-, y+[, z-, z+])."""
+    ndim = len(shape)
+    G = np.ones(shape)
+    for a in range(ndim):           # a = 0: x (last array axis)
+        n = shape[ndim - 1 - a]
+        prof = cerjan(n, width, alpha, faces[2 * a], faces[2 * a + 1])
+        sh = [1] * ndim
+        sh[ndim - 1 - a] = n
+        G = G * prof.reshape(sh)
+    return G
+
+
 def forward(v, h, dt, r, nsteps, sources=(), receivers=None, periodic=False, u0=None, um1=None,
-            store_states=False):
+            store_states=False, damping=None):
     """Run ``nsteps`` leapfrog steps of u_tt = v^2 L u + sum_s s_s(t) delta_s.
 
     v          velocity, dense (nz, ny, nx) / (ny, nx) / (nx,), m/s
@@ -268,6 +302,8 @@ def forward(v, h, dt, r, nsteps, sources=(), receivers=None, periodic=False, u0=
                produces u^{n+1}, scaled by dt^2 / h^ndim (discrete delta)
     receivers  int array [nrec, ndim] of (x, y, z) positions; traces[n][j] = u^{n+1}(x_j)
     u0, um1    initial u^0 and u^{-1} (default zero)
+    damping    optional (width, alpha[, faces]): a Cerjan sponge (see damping_field); both
+               time levels are scaled by G every step: u^{n+1} = G (2u^n - G u^{n-1} + ...)
 
     Returns dict(u=u^T, u_prev=u^{T-1}, traces=[T, nrec], states=[T+1, ...] or None).
     """
@@ -285,10 +321,13 @@ def forward(v, h, dt, r, nsteps, sources=(), receivers=None, periodic=False, u0=
         rec_idx = linear_index(shape, receivers)
     traces = np.zeros((nsteps, rec_idx.shape[0]), dtype=np.float64)
     states = np.zeros((nsteps + 1,) + shape, dtype=np.float64) if store_states else None
+    G = None
+    if damping is not None:
+        G = np.ascontiguousarray(damping_field(shape, *damping))
     st = _lib().fdo_forward(
         ndim, _ptr(n), r, _ptr(w), float(h), float(dt), _ptr(m), int(periodic), int(nsteps),
         int(src_idx.shape[0]), _ptr(src_idx), _ptr(src), int(rec_idx.shape[0]), _ptr(rec_idx),
-        _ptr(traces), _ptr(u), _ptr(up), _ptr(states),
+        _ptr(traces), _ptr(u), _ptr(up), _ptr(states), _ptr(G),
     )
     _check(st, "forward")
     return {"u": u, "u_prev": up, "traces": traces, "states": states}

@@ -161,11 +161,16 @@ int fdo_laplacian(int ndim, const int64_t *n, int r, const double *w, double h, 
  *   src_idx[s]  linear index of source s; src[n * nsrc + s] its sample at step n
  *   rec_idx[j]  linear index of receiver j; traces[n * nrec + j]
  *   states      optional [nsteps + 1][N]: u^0 .. u^T
+ *   damp        optional [N]: the absorbing-sponge factor G of each point (1 outside the
+ *               sponge).  The sponge of Sec. 1 (after Cerjan et al.) scales both time
+ *               levels by G at every step; fused into the update this is
+ *                   u^{n+1} = G (2 u^n - G u^{n-1} + dt^2 m L u^n),
+ *               unchanged where G = 1.  Sources are added after it.
  */
 int fdo_forward(int ndim, const int64_t *n, int r, const double *w, double h, double dt,
                 const double *m, int periodic, int64_t nsteps, int64_t nsrc, const int64_t *src_idx,
                 const double *src, int64_t nrec, const int64_t *rec_idx, double *traces,
-                double *u_cur, double *u_prev, double *states)
+                double *u_cur, double *u_prev, double *states, const double *damp)
 {
     int st = check_grid(ndim, n, r, w, h);
     if (st) return st;
@@ -194,7 +199,12 @@ int fdo_forward(int ndim, const int64_t *n, int r, const double *w, double h, do
             for (int64_t j = 0; j < g.n[1]; ++j)
                 for (int64_t i = 0; i < g.n[0]; ++i) {
                     int64_t p = (k * g.n[1] + j) * g.n[0] + i;
-                    u_next[p] = 2.0 * u_cur[p] - u_prev[p] + dt2 * m[p] * laplacian_at(&g, &pf, i, j, k);
+                    if (damp) {
+                        const double G = damp[p];
+                        u_next[p] = G * (2.0 * u_cur[p] - G * u_prev[p] + dt2 * m[p] * laplacian_at(&g, &pf, i, j, k));
+                    } else {
+                        u_next[p] = 2.0 * u_cur[p] - u_prev[p] + dt2 * m[p] * laplacian_at(&g, &pf, i, j, k);
+                    }
                 }
         for (int64_t s = 0; s < nsrc; ++s)
             u_next[src_idx[s]] += src_scale * src[step * nsrc + s];
