@@ -36,6 +36,9 @@ PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "fwd_r4_512_traffic.json")
 KERNEL_SOURCES = ["paper_1410_1387_amd/csrc/fd_stencil.h", "paper_1410_1387_amd/csrc/fd_fwd_f32.hip",
                   "paper_1410_1387_amd/csrc/fd_types.h"]
 VTI_PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "vti_r12_8_512_traffic.json")
+ADJ_PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "adj_r4_256_traffic.json")
+ADJ_KERNEL_SOURCES = ["paper_1410_1387_amd/csrc/fd_stencil.h", "paper_1410_1387_amd/csrc/fd_adj_f32.hip",
+                      "paper_1410_1387_amd/csrc/fd_types.h"]
 VTI_KERNEL_SOURCES = ["paper_1410_1387_amd/csrc/fd_stencil.h", "paper_1410_1387_amd/csrc/fd_vti.h",
                       "paper_1410_1387_amd/csrc/fd_vti_f32.hip", "paper_1410_1387_amd/csrc/fd_types.h"]
 # the paper's best VTI rates (Mpts/s, FP32, R_xy = 12, R_z = 8), quoted as context only
@@ -266,7 +269,8 @@ def summarize_prof(d: str, out_json: str = PROFILE_TRAFFIC):
         "python3 bench.py --steps 1 --warmup 0 --no-cpu --copy-probe",
     ]
     for tag, out_path, sources, algo in (("fwd_kernel", out_json, KERNEL_SOURCES, 16.0 * 512 ** 3),
-                                         ("vti_kernel", VTI_PROFILE_TRAFFIC, VTI_KERNEL_SOURCES, 36.0 * 512 ** 3)):
+                                         ("vti_kernel", VTI_PROFILE_TRAFFIC, VTI_KERNEL_SOURCES, 36.0 * 512 ** 3),
+                                         ("adj_kernel", ADJ_PROFILE_TRAFFIC, ADJ_KERNEL_SOURCES, 28.0 * 256 ** 3)):
         cands = [k for k in fetch if tag in k]
         if not cands:
             continue
@@ -367,14 +371,55 @@ def run_gradient():
     n3 = case.n ** 3
     finite = bool(torch.isfinite(g).all().item())
     log(f"gradient: forward {tf:.3f} s, backward {tb:.3f} s, J {J:.4e}, finite={finite}")
+    adj_ms = time_adjoint_kernel(v0t, case, dt, rec)
+    algo = 28.0 * n3
+    achieved = algo / (adj_ms * 1e-3) / 1e9
+    tr = measured_traffic(ADJ_PROFILE_TRAFFIC, ADJ_KERNEL_SOURCES)
+    log(f"adjoint kernel: {adj_ms * 1e3:.1f} us/launch, {achieved:.0f} GB/s algorithmic")
     return {
         "workload": f"gradient_{case.n}_r{case.r}_fp32_{case.nsteps}steps_ckpt{case.ckpt}",
         "gradient_s": round(tf + tb, 4), "forward_with_checkpoints_s": round(tf, 4), "backward_s": round(tb, 4),
         "gpts_per_s": round(n3 * case.nsteps / (tf + tb) / 1e9, 2),
         "unit": "grid points x time steps per second of a full gradient (forward + recompute + adjoint)",
-        "adjoint_step_us": round(tb / case.nsteps * 1e6, 1), "misfit": J, "finite": finite,
+        "backward_step_us": round(tb / case.nsteps * 1e6, 1), "misfit": J, "finite": finite,
         "receivers": len(rec), "checkpoints": (case.nsteps + case.ckpt - 1) // case.ckpt,
+        "adjoint_kernel_roofline": {
+            "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None if tr is None else round(tr / (adj_ms * 1e-3) / 1e9, 1),
+            "algorithmic_bytes_per_launch": algo, "launch_us": round(adj_ms * 1e3, 2),
+        },
     }
+
+
+def time_adjoint_kernel(v, case, dt, rec, reps=200):
+    """Average duration of one adjoint-kernel launch at the gradient workload's size (read
+    mu^{k+1}, mu^{k+2}, c, u^{k-1}, g; write mu^k, g: 28 B/pt): one-step segments need no
+    recompute, so each fd_adjoint_segment call is exactly one adjoint launch."""
+    import torch
+
+    from paper_1410_1387_amd import Propagator
+    from paper_1410_1387_amd import fdwave as F
+
+    p = Propagator(v, case.r, case.h, dt, "f32", max_sources=1, max_receivers=len(rec))
+    p.inject(p.ricker(case.nsteps, case.f0), case.source)
+    p.record(rec, case.nsteps)
+    fb = p.field_bytes
+    z = lambda nbytes: torch.zeros(nbytes // 4, dtype=torch.float32, device=v.device)  # noqa: E731
+    u_cur, u_prev, mu, g = z(fb), z(fb), z(2 * fb), z(fb)
+    resid = torch.zeros((case.nsteps, len(rec)), dtype=torch.float32, device=v.device)
+    stream = torch.cuda.current_stream()
+    for k in range(5):
+        F.fd_adjoint_segment(p.ctx, u_cur, u_prev, k, k + 1, None, mu, resid, 1.0, g)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for k in range(reps):
+        F.fd_adjoint_segment(p.ctx, u_cur, u_prev, k + 1, k + 2, None, mu, resid, 1.0, g)
+    e1.record(stream)
+    p.sync()
+    ms = e0.elapsed_time(e1) / reps
+    p.close()
+    return ms
 
 
 def serving_requests(nreq=256):

@@ -140,6 +140,18 @@ int fd_set_stream(fd_ctx *ctx, void *stream);
 int fd_inject(fd_ctx *ctx, const void *wavelet, int64_t nsamp, const int64_t pos[3], double amp);
 int fd_clear_sources(fd_ctx *ctx);
 
+/* Absorbing sponge (Sec. 1: the domain is embedded in a damping region, after Cerjan et
+ * al.; the paper gives neither profile nor constants).  In a strip of `width` points at
+ * each face selected by `faces` (bit 0 x-, 1 x+, 2 y-, 3 y+, 4 z-, 5 z+ of the grid's
+ * axes; a 2-D grid uses bits 0-3), the point at distance i from the face (i = 0 outermost)
+ * has the factor exp(-(alpha (width - i))^2); factors of overlapping strips multiply and
+ * G = 1 elsewhere.  Every step then computes u^{n+1} = G (2u^n - G u^{n-1} + c Lh u^n)
+ * (both time levels damped) before adding sources.  Cerjan's constants are width = 20,
+ * alpha = 0.015.  width = 0 or faces = 0 switches the sponge off (the update is then
+ * bitwise the undamped one).  Zero boundary only (FD_E_STATE otherwise); a damped context
+ * has no adjoint (fd_adjoint_segment returns FD_E_STATE). */
+int fd_set_damping(fd_ctx *ctx, int width, double alpha, int faces);
+
 /* Record u^{n+1} at receiver positions after every step (fused into the stencil kernel).
  *   pos     host, int32 [nrec][3] (x, y, z); z ignored in 2-D
  *   traces  device, dtype, time-major [cap][nrec]; row i holds the step that starts

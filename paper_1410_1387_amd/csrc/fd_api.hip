@@ -73,7 +73,7 @@ struct Layout {
     int64_t pxy, off0, elems;
     size_t field_bytes;      // one padded field, rounded to 256 bytes
     // workspace offsets
-    size_t o_desc, o_partial, o_minmax, o_buf0, o_buf1, o_c, o_evptr, o_ev, o_src, total;
+    size_t o_desc, o_partial, o_minmax, o_buf0, o_buf1, o_c, o_evptr, o_ev, o_src, o_damp, total;
     int64_t ncol;
 };
 
@@ -123,6 +123,8 @@ bool make_layout(const fd_grid *g, int r, fd_dtype dt, int64_t max_src, int64_t 
     o += align_up(std::max<int64_t>(1, max_src + max_rec) * (int64_t)sizeof(Event), 256);
     L->o_src = o;
     o += align_up(std::max<int64_t>(1, max_src) * (int64_t)sizeof(SourceInfo), 256);
+    L->o_damp = o;
+    o += align_up((L->knx + L->kny + L->knz) * (int64_t)L->esize, 256);
     L->total = o;
     return true;
 }
@@ -562,6 +564,47 @@ extern "C" int fd_clear_sources(fd_ctx *ctx)
     return upload_tables(ctx);
 }
 
+// Cerjan sponge factors along one axis of n points (distance i from a damped face,
+// i < width: exp(-(alpha (width - i))^2); overlapping strips multiply).
+static void sponge_profile(int64_t n, int width, double alpha, bool lo, bool hi, double *g)
+{
+    for (int64_t i = 0; i < n; ++i) g[i] = 1.0;
+    for (int64_t i = 0; i < std::min<int64_t>(width, n); ++i) {
+        const double a = alpha * (double)(width - i);
+        const double f = std::exp(-a * a);
+        if (lo) g[i] *= f;
+        if (hi) g[n - 1 - i] *= f;
+    }
+}
+
+extern "C" int fd_set_damping(fd_ctx *ctx, int width, double alpha, int faces)
+{
+    int st = check_ctx(ctx);
+    if (st) return st;
+    if (width < 0 || !(alpha >= 0) || !std::isfinite(alpha) || faces < 0 || faces > 63)
+        return fail(FD_E_INVAL, "fd_set_damping: width >= 0, alpha >= 0, faces a 6-bit mask");
+    if (ctx->bc != FD_BC_ZERO && width > 0) return fail(FD_E_STATE, "fd_set_damping: zero boundary only");
+    const Layout &L = ctx->L;
+    if (width == 0 || faces == 0) {
+        ctx->desc.damp = nullptr;
+    } else {
+        // grid faces -> kernel axes: a 2-D grid's y is the kernel's z, the kernel y is unit
+        const bool nd3 = L.ndim == 3;
+        const int fz = nd3 ? (faces >> 4) & 3 : (faces >> 2) & 3;
+        const int fy = nd3 ? (faces >> 2) & 3 : 0;
+        std::vector<double> g((size_t)(L.knx + L.kny + L.knz));
+        sponge_profile(L.knx, width, alpha, faces & 1, faces & 2, g.data());
+        sponge_profile(L.kny, fy ? width : 0, alpha, fy & 1, fy & 2, g.data() + L.knx);
+        sponge_profile(L.knz, width, alpha, fz & 1, fz & 2, g.data() + L.knx + L.kny);
+        std::vector<float> gf;
+        if (ctx->dtype == FD_F32) gf.assign(g.begin(), g.end());
+        HIP_TRY(ctx, hipMemcpyAsync(ctx->ws + L.o_damp, ctx->dtype == FD_F32 ? (const void *)gf.data() : g.data(),
+                                    g.size() * L.esize, hipMemcpyHostToDevice, ctx->stream));
+        ctx->desc.damp = ctx->ws + L.o_damp;
+    }
+    return upload_tables(ctx);
+}
+
 extern "C" int fd_record(fd_ctx *ctx, const int32_t *pos, int64_t nrec, void *traces, int64_t cap)
 {
     int st = check_ctx(ctx);
@@ -716,6 +759,7 @@ extern "C" int fd_adjoint_segment(fd_ctx *ctx, const void *u_ckpt_cur, const voi
     int st = check_ctx(ctx);
     if (st) return st;
     if (ctx->bc != FD_BC_ZERO) return fail(FD_E_STATE, "fd_adjoint_segment: zero boundary only");
+    if (ctx->desc.damp) return fail(FD_E_STATE, "fd_adjoint_segment: the adjoint of the damped scheme is not built");
     const int64_t nk = k_hi - k_lo;
     if (k_lo < 0 || nk < 1 || !u_ckpt_cur || !u_ckpt_prev || !mu || !grad || (nk > 1 && !ring))
         return fail(FD_E_INVAL, "fd_adjoint_segment: bad arguments");

@@ -395,6 +395,17 @@ __device__ __forceinline__ void fwd_tile(const ShotDesc &s, const typename C::ty
     int bz = g.z0 % NB;              // LDS buffer of plane z
     int bh = (g.z0 + HOFF) % NB;     // LDS buffer of plane z + HOFF
 
+    // absorbing sponge: G = gx gy gz scales both time levels (1 outside the sponge)
+    const T *__restrict__ damp = static_cast<const T *>(s.damp);
+    T gxy[EY][VEC];
+    if (damp) {
+#pragma unroll
+        for (int e = 0; e < EY; ++e)
+#pragma unroll
+            for (int v = 0; v < VEC; ++v)
+                gxy[e][v] = (g.rin[e] && g.gx + v < s.nx) ? damp[g.gx + v] * damp[s.nx + g.gy + e] : T(1);
+    }
+
     for (int zb = g.z0; zb < g.z1; zb += 2) {
         static_for<2>([&](auto st_) __attribute__((always_inline)) {
             constexpr int st = decltype(st_)::value;
@@ -469,7 +480,12 @@ __device__ __forceinline__ void fwd_tile(const ShotDesc &s, const typename C::ty
 #pragma unroll
                     for (int l = 1; l <= R; ++l)
                         acc = fma_t(T(W.w[l]), (q[R + l][e][v] - u0) + (q[R - l][e][v] - u0), acc);
-                    un[e][v] = fma_t(cv[cs][e][v], acc, T(2) * u0 - pv[cs][e][v]);
+                    if (damp) {
+                        const T G = gxy[e][v] * damp[s.nx + s.ny + z];
+                        un[e][v] = G * fma_t(cv[cs][e][v], acc, T(2) * u0 - G * pv[cs][e][v]);
+                    } else {
+                        un[e][v] = fma_t(cv[cs][e][v], acc, T(2) * u0 - pv[cs][e][v]);
+                    }
                 }
             }
 

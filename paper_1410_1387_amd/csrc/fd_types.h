@@ -37,6 +37,7 @@ struct ShotDesc {
     const SourceInfo *src;
     void *traces;          // [cap][nrec] of dtype
     int64_t nrec, rec_base, rec_cap;
+    const void *damp;      // absorbing sponge: per-axis factors [nx | ny | nz] of dtype, or null
 };
 
 // Per-launch arguments (passed by value).

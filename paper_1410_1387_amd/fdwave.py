@@ -29,7 +29,7 @@ STATUS_NAMES = {
 # every symbol include/fdwave.h declares
 EXPORTS = [
     "fd_weights", "fd_dt_max", "fd_field_bytes", "fd_workspace_bytes", "fd_create", "fd_destroy",
-    "fd_set_stream", "fd_inject", "fd_clear_sources", "fd_record", "fd_ricker", "fd_step", "fd_sync",
+    "fd_set_stream", "fd_inject", "fd_clear_sources", "fd_set_damping", "fd_record", "fd_ricker", "fd_step", "fd_sync",
     "fd_get_step", "fd_get_state", "fd_set_state", "fd_step_explicit", "fd_adjoint_segment",
     "fd_gradient_finish", "fd_batch_workspace_bytes", "fd_batch_create", "fd_batch_destroy",
     "fd_batch_set", "fd_batch_step", "fd_copy_probe", "fd_kernel_config", "fd_set_tuning",
@@ -74,6 +74,7 @@ def lib():
             "fd_set_stream": (ctypes.c_int, [P, P]),
             "fd_inject": (ctypes.c_int, [P, P, I64, ctypes.POINTER(I64), D]),
             "fd_clear_sources": (ctypes.c_int, [P]),
+            "fd_set_damping": (ctypes.c_int, [P, ctypes.c_int, D, ctypes.c_int]),
             "fd_record": (ctypes.c_int, [P, ctypes.POINTER(I32), I64, P, I64]),
             "fd_ricker": (ctypes.c_int, [P, I64, D, D, D, ctypes.c_int, P]),
             "fd_step": (ctypes.c_int, [P, I64]),
@@ -216,6 +217,10 @@ def fd_inject(ctx: int, wavelet, pos, amp: float = 1.0):
 
 def fd_clear_sources(ctx: int):
     _check(lib().fd_clear_sources(ctx), "fd_clear_sources")
+
+
+def fd_set_damping(ctx: int, width: int, alpha: float = 0.015, faces: int = 63):
+    _check(lib().fd_set_damping(ctx, int(width), float(alpha), int(faces)), "fd_set_damping")
 
 
 def fd_record(ctx: int, positions, traces, cap: int):

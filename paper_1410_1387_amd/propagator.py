@@ -83,6 +83,11 @@ class Propagator:
         self._wavelets.append(wavelet)
         F.fd_inject(self.ctx, wavelet, pos, amp)
 
+    def set_damping(self, width: int = 20, alpha: float = 0.015, faces: int = 63):
+        """Absorbing sponge of `width` points at the faces in the bit mask `faces` (bit 0 x-,
+        1 x+, 2 y-, 3 y+, 4 z-, 5 z+); width = 0 switches it off."""
+        F.fd_set_damping(self.ctx, width, alpha, faces)
+
     def clear_sources(self):
         F.fd_clear_sources(self.ctx)
         self._wavelets = []

@@ -331,3 +331,78 @@ def test_error_paths_leave_state_untouched(oracle_mod):
     assert torch.equal(p.state()[0], u5)
     p.sync()
     p.close()
+
+
+# ----------------------------------------------------------------------------- absorbing sponge
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("shape,r,width,faces", [((41, 50, 70), 4, 8, 63), ((30, 36, 29), 2, 5, 0b101110),
+                                                   ((120, 140), 4, 20, 15)])
+def test_sponge_vs_oracle(oracle_mod, shape, r, width, faces, dtype):
+    # faces: bit 0 x-, 1 x+, 2 y-, 3 y+, 4 z-, 5 z+ (a 2-D grid's y is its second axis)
+    h = 10.0
+    nd = len(shape)
+    v = workloads.layered_velocity(shape, seed=31)
+    dt = 0.5 * oracle_mod.dt_max(nd, r, h, v.max())
+    T = 160
+    src = tuple(s // 2 for s in shape[::-1])
+    rec = np.array([tuple([c] + list(src[1:])) for c in range(0, shape[-1], 3)])
+    alpha = 0.05
+    flags = tuple(bool(faces >> b & 1) for b in range(2 * nd))
+    ref = oracle_mod.forward(v, h, dt, r, T, [(src, oracle_mod.ricker(T, dt, 30.0, 0.03))], rec,
+                             damping=(width, alpha, flags))
+    got = run_gpu(v, r, h, dt, T, dtype, receivers=rec, ricker=(src, 30.0, 0.03), damping=(width, alpha, faces),
+                  label="sponge")
+    eu, et = rel_l2(got["u"], ref["u"]), rel_l2(got["traces"], ref["traces"])
+    say(f"sponge {dtype} {shape} r={r}: rel L2 u {eu:.2e} traces {et:.2e}")
+    assert eu <= TOL[dtype] and et <= TOL[dtype]
+
+
+def test_sponge_off_is_bitwise_undamped(oracle_mod):
+    shape, r, h, T = (33, 35, 37), 4, 10.0, 60
+    v = workloads.layered_velocity(shape, seed=2)
+    dt = 0.5 * oracle_mod.dt_max(3, r, h, v.max())
+    a = run_gpu(v, r, h, dt, T, "f32", ricker=((18, 17, 16), 30.0, 0.03), label="no sponge")
+    b = run_gpu(v, r, h, dt, T, "f32", ricker=((18, 17, 16), 30.0, 0.03), damping=(0, 0.015, 63), label="width 0")
+    c = run_gpu(v, r, h, dt, T, "f32", ricker=((18, 17, 16), 30.0, 0.03), damping=(6, 0.0, 63), label="alpha 0")
+    assert np.array_equal(a["u"], b["u"]) and np.array_equal(a["u"], c["u"])
+
+
+def test_sponge_in_batch_and_no_adjoint(oracle_mod):
+    import torch
+
+    from paper_1410_1387_amd import Propagator
+    from paper_1410_1387_amd import fdwave as F
+
+    shape, r, h, T = (26, 30, 34), 4, 10.0, 40
+    v = workloads.layered_velocity(shape, seed=9)
+    dt = 0.5 * oracle_mod.dt_max(3, r, h, v.max())
+    vt = torch.tensor(v, dtype=torch.float32, device="cuda")
+
+    def make(damped):
+        p = Propagator(vt, r, h, dt, "f32")
+        if damped:
+            p.set_damping(6, 0.06, 63)
+        p.inject(p.ricker(T, 30.0, 0.03), (17, 15, 13))
+        return p
+
+    alone = make(True)
+    alone.step(T)
+    ua = alone.state()[0].cpu().numpy()
+    pa, pb = make(True), make(False)
+    bws = torch.empty(F.fd_batch_workspace_bytes(2), dtype=torch.uint8, device="cuda")
+    b = F.fd_batch_create(2, bws, F.stream_ptr())
+    F.fd_batch_set(b, [pa.ctx, pb.ctx], [T, T])
+    F.fd_batch_step(b, T)
+    torch.cuda.synchronize()
+    assert np.array_equal(pa.state()[0].cpu().numpy(), ua)
+    assert not np.array_equal(pb.state()[0].cpu().numpy(), ua)
+    F.fd_batch_destroy(b)
+    fb = alone.field_bytes
+    z = lambda: torch.zeros(fb // 4, dtype=torch.float32, device="cuda")  # noqa: E731
+    with pytest.raises(F.FdError) as e:
+        F.fd_adjoint_segment(alone.ctx, z(), z(), 0, 1, None, torch.zeros(fb // 2, device="cuda"), None, 1.0, z())
+    assert e.value.status == F.FD_E_STATE
+    for p in (alone, pa, pb):
+        p.close()
