@@ -174,6 +174,22 @@ int fd_ricker(void *out, int64_t nsamp, double dt, double f0, double t0, fd_dtyp
  * before anything is enqueued), FD_E_STATE if poisoned. */
 int fd_step(fd_ctx *ctx, int64_t nsteps);
 
+/* Two steps per launch (temporal blocking) for fd_step: each launch takes (u^n, u^{n-1})
+ * to (u^{n+1}, u^{n+2}) of the same scheme (Sec. 1 time scheme), reading u^n, u^{n-1} and c
+ * once and writing both new levels (20 B per point per two steps instead of 32).  The
+ * result is bitwise that of single steps.  aux: device, caller-owned, 256-byte aligned,
+ * >= 2 * fd_field_bytes bytes, borrowed until disabled or the context is destroyed; it
+ * is zeroed here (on the context stream).  fd_step then runs groups of four steps as two
+ * two-step launches (through aux and back, so the context's fields keep their roles) and
+ * any remainder as single steps.  Periodic or damped contexts keep single steps.
+ * config: index of the tile shape (0 = default).  aux = NULL disables.  On MI355X this
+ * path moves 20 instead of 32 bytes per point and two steps but is latency-bound (one
+ * workgroup per compute unit, two barriers per plane): 228 Gpts/s against 342 for single
+ * steps at 512^3, so it is off unless enabled.  Errors:
+ * FD_E_INVAL (no two-step kernel: 3-D FP32 with r = 4 only; misaligned aux), FD_E_RANGE
+ * (config), FD_E_NOMEM (aux too small). */
+int fd_set_time_blocking(fd_ctx *ctx, void *aux, size_t aux_bytes, int config);
+
 /* Wait for the context's stream; reports asynchronous device errors (FD_E_DEVICE). */
 int fd_sync(fd_ctx *ctx);
 

@@ -19,7 +19,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfdwave.so")
 SOURCES = ["fd_api.hip", "fd_util.hip", "fd_fwd_f32.hip", "fd_fwd_f64.hip", "fd_adj_f32.hip", "fd_adj_f64.hip",
-           "fd_vti_api.hip", "fd_vti_f32.hip", "fd_vti_f64.hip"]
+           "fd_vti_api.hip", "fd_vti_f32.hip", "fd_vti_f64.hip", "fd_fwd2_f32.hip"]
 ARCH = "gfx950"
 
 

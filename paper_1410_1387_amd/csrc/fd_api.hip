@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "../../include/fdwave.h"
+#include "fd_fwd2.h"
 #include "fd_stencil.h"
 #include "fd_types.h"
 #include "fd_util.h"
@@ -240,6 +241,11 @@ struct fd_ctx {
     int64_t step;
     bool poisoned;
     int xcd_remap;
+    // two-step forward (temporal blocking): two caller-provided padded fields
+    void *aux[2];
+    const Fwd2Entry *k2;
+    int zch2;
+    int64_t tiles2_x, tiles2_y, chunks2_z;
 
     void *buf(int i) const { return ws + (i == 0 ? L.o_buf0 : L.o_buf1); }
     void *cfield() const { return ws + L.o_c; }
@@ -656,6 +662,53 @@ static LaunchArgs direct_args(const fd_ctx *c, int64_t step)
 
 static int64_t nwg_of(const fd_ctx *c) { return c->tiles_x * c->tiles_y * c->chunks_z; }
 
+static void launch_two_step(fd_ctx *c, const void *cur, const void *prev, void *out1, void *out2, int64_t step)
+{
+    Fwd2Args a;
+    std::memset(&a, 0, sizeof(a));
+    a.shot = c->d_desc();
+    a.cur = cur;
+    a.prev = prev;
+    a.out1 = out1;
+    a.out2 = out2;
+    a.step = step;
+    a.zch = c->zch2;
+    a.tiles_x = (int32_t)c->tiles2_x;
+    a.tiles_y = (int32_t)c->tiles2_y;
+    a.chunks_z = (int32_t)c->chunks2_z;
+    a.xcd_remap = c->xcd_remap;
+    c->k2->launch(a, (int)(c->tiles2_x * c->tiles2_y * c->chunks2_z), c->stream);
+}
+
+extern "C" int fd_set_time_blocking(fd_ctx *ctx, void *aux, size_t aux_bytes, int config)
+{
+    int st = check_ctx(ctx);
+    if (st) return st;
+    if (!aux) {
+        ctx->aux[0] = ctx->aux[1] = nullptr;
+        ctx->k2 = nullptr;
+        return FD_OK;
+    }
+    const Layout &L = ctx->L;
+    int count = 0;
+    const Fwd2Entry *tab = (L.ndim == 3 && ctx->dtype == FD_F32) ? fwd2_configs_f32(ctx->r, &count) : nullptr;
+    if (!tab || count == 0) return fail(FD_E_INVAL, "fd_set_time_blocking: no two-step kernel for this dtype/r/ndim");
+    if (config < 0 || config >= count) return fail(FD_E_RANGE, "fd_set_time_blocking: config %d of %d", config, count);
+    if (reinterpret_cast<uintptr_t>(aux) % 256 != 0) return fail(FD_E_INVAL, "fd_set_time_blocking: aux not 256-byte aligned");
+    if (aux_bytes < 2 * L.field_bytes)
+        return fail(FD_E_NOMEM, "fd_set_time_blocking: aux %zu bytes < %zu needed", aux_bytes, 2 * L.field_bytes);
+    // the kernel writes interiors only: ghosts and padding of the extra fields stay zero
+    HIP_TRY(ctx, hipMemsetAsync(aux, 0, 2 * L.field_bytes, ctx->stream));
+    ctx->aux[0] = aux;
+    ctx->aux[1] = (char *)aux + L.field_bytes;
+    ctx->k2 = &tab[config];
+    ctx->tiles2_x = (L.knx + ctx->k2->bx - 1) / ctx->k2->bx;
+    ctx->tiles2_y = (L.kny + ctx->k2->by - 1) / ctx->k2->by;
+    ctx->zch2 = choose_zch(ctx->tiles2_x * ctx->tiles2_y, L.knz, ctx->r, resident_slots(ctx->k2->kernel, ctx->k2->nt));
+    ctx->chunks2_z = (L.knz + ctx->zch2 - 1) / ctx->zch2;
+    return FD_OK;
+}
+
 extern "C" int fd_step(fd_ctx *ctx, int64_t nsteps)
 {
     int st = check_ctx(ctx);
@@ -667,7 +720,20 @@ extern "C" int fd_step(fd_ctx *ctx, int64_t nsteps)
                     (long long)ctx->rec_cap, (long long)ctx->step, (long long)nsteps, (long long)ctx->rec_base);
     const int64_t nwg = nwg_of(ctx);
     const Geom gm = geom_of(ctx->L);
-    for (int64_t i = 0; i < nsteps; ++i) {
+    int64_t i = 0;
+    if (ctx->k2 && ctx->bc == FD_BC_ZERO && !ctx->desc.damp) {
+        // pairs of two-step launches: (u^n, u^{n-1}) -> aux -> back into the two context
+        // fields with their usual roles, so every other call sees the usual layout
+        for (; i + 4 <= nsteps; i += 4) {
+            const int64_t n = ctx->step;
+            launch_two_step(ctx, ctx->buf((int)(n & 1)), ctx->buf((int)((n + 1) & 1)), ctx->aux[0], ctx->aux[1], n);
+            HIP_TRY(ctx, hipGetLastError());
+            launch_two_step(ctx, ctx->aux[1], ctx->aux[0], ctx->buf((int)((n + 3) & 1)), ctx->buf((int)(n & 1)), n + 2);
+            HIP_TRY(ctx, hipGetLastError());
+            ctx->step += 4;
+        }
+    }
+    for (; i < nsteps; ++i) {
         if (ctx->bc == FD_BC_PERIODIC)
             HIP_TRY(ctx, launch_halo_periodic((int)ctx->dtype, gm, ctx->r, ctx->L.ndim == 3 ? ctx->r : 0, ctx->r,
                                               ctx->buf((int)(ctx->step & 1)), ctx->stream));

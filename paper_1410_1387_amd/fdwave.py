@@ -30,7 +30,7 @@ STATUS_NAMES = {
 EXPORTS = [
     "fd_weights", "fd_dt_max", "fd_field_bytes", "fd_workspace_bytes", "fd_create", "fd_destroy",
     "fd_set_stream", "fd_inject", "fd_clear_sources", "fd_set_damping", "fd_record", "fd_ricker", "fd_step", "fd_sync",
-    "fd_get_step", "fd_get_state", "fd_set_state", "fd_step_explicit", "fd_adjoint_segment",
+    "fd_get_step", "fd_get_state", "fd_set_time_blocking", "fd_set_state", "fd_step_explicit", "fd_adjoint_segment",
     "fd_gradient_finish", "fd_batch_workspace_bytes", "fd_batch_create", "fd_batch_destroy",
     "fd_batch_set", "fd_batch_step", "fd_copy_probe", "fd_kernel_config", "fd_set_tuning",
     "fd_last_error",
@@ -78,6 +78,7 @@ def lib():
             "fd_record": (ctypes.c_int, [P, ctypes.POINTER(I32), I64, P, I64]),
             "fd_ricker": (ctypes.c_int, [P, I64, D, D, D, ctypes.c_int, P]),
             "fd_step": (ctypes.c_int, [P, I64]),
+            "fd_set_time_blocking": (ctypes.c_int, [P, P, SZ, ctypes.c_int]),
             "fd_sync": (ctypes.c_int, [P]),
             "fd_get_step": (ctypes.c_int, [P, ctypes.POINTER(I64)]),
             "fd_get_state": (ctypes.c_int, [P, P, P, ctypes.POINTER(I64), ctypes.c_int]),
@@ -241,6 +242,11 @@ def fd_ricker(out, dt: float, f0: float, t0: float, stream):
 
 def fd_step(ctx: int, nsteps: int):
     _check(lib().fd_step(ctx, int(nsteps)), "fd_step")
+
+
+def fd_set_time_blocking(ctx: int, aux, config: int = 0):
+    _check(lib().fd_set_time_blocking(ctx, ptr(aux), 0 if aux is None else aux.numel() * aux.element_size(),
+                                      int(config)), "fd_set_time_blocking")
 
 
 def fd_sync(ctx: int):

@@ -88,6 +88,16 @@ class Propagator:
         1 x+, 2 y-, 3 y+, 4 z-, 5 z+); width = 0 switches it off."""
         F.fd_set_damping(self.ctx, width, alpha, faces)
 
+    def enable_time_blocking(self, config: int = 0):
+        """Run fd_step two time steps per launch (bitwise the same result); allocates the
+        two extra padded fields the two-step kernel writes into."""
+        self.aux = torch.empty(2 * self.field_bytes, dtype=torch.uint8, device=self.device)
+        F.fd_set_time_blocking(self.ctx, self.aux, config)
+
+    def disable_time_blocking(self):
+        F.fd_set_time_blocking(self.ctx, None)
+        self.aux = None
+
     def clear_sources(self):
         F.fd_clear_sources(self.ctx)
         self._wavelets = []

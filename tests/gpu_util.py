@@ -18,13 +18,14 @@ def say(msg: str):
 
 
 def run_gpu(v, r, h, dt, T, dtype="f32", sources=(), receivers=None, bc="zero", u0=None, um1=None,
-            tuning=None, ricker=None, label="", damping=None):
+            tuning=None, ricker=None, label="", damping=None, two_step=None):
     """Forward T steps on the GPU.
 
     sources   [(pos, samples ndarray)] -- samples are an input shared with the oracle
     ricker    optional (pos, f0, t0): a Ricker source whose samples the GPU computes itself
     tuning    optional (config, zchunk) for fd_set_tuning before the context is created
     damping   optional (width, alpha, faces mask) for the absorbing sponge
+    two_step  optional tile config index: run fd_step two steps per launch
     Returns dict(u, u_prev, traces, step, config).
     """
     import torch
@@ -47,6 +48,8 @@ def run_gpu(v, r, h, dt, T, dtype="f32", sources=(), receivers=None, bc="zero", 
             F.fd_set_tuning(dtype, r, ndim, 0, 0)
     if damping is not None:
         p.set_damping(*damping)
+    if two_step is not None:
+        p.enable_time_blocking(two_step)
     for pos, wav in sources:
         p.inject(torch.tensor(np.asarray(wav), dtype=tdt, device="cuda"), pos)
     if ricker is not None:

@@ -406,3 +406,61 @@ def test_sponge_in_batch_and_no_adjoint(oracle_mod):
     assert e.value.status == F.FD_E_STATE
     for p in (alone, pa, pb):
         p.close()
+
+
+# ----------------------------------------------------------------------------- two steps per launch
+
+
+def _two_step_case(shape, seed):
+    nz, ny, nx = shape
+    rng = np.random.default_rng(seed)
+    src = [(int(rng.integers(0, nx)), int(rng.integers(0, ny)), int(rng.integers(0, nz))) for _ in range(3)]
+    src += [(min(nx - 1, 64), min(ny - 1, 31), nz // 2), (0, 0, 0), (nx - 1, ny - 1, nz - 1)]  # tile edges, corners
+    rec = _receivers_3d(shape, nz // 2)
+    return src, rec
+
+
+@pytest.mark.parametrize("config", [0, 1, 2])
+@pytest.mark.parametrize("shape,T", [((45, 70, 130), 41), ((7, 5, 9), 14), ((130, 33, 65), 22), ((64, 32, 64), 8)])
+def test_two_step_bitwise(oracle_mod, shape, T, config):
+    # two steps per launch repeat the single-step arithmetic exactly: fields and traces
+    # are bitwise those of single steps (T not a multiple of 4 exercises the remainder)
+    r, h = 4, 10.0
+    v = workloads.layered_velocity(shape, seed=17)
+    dt = 0.45 * oracle_mod.dt_max(3, r, h, v.max())
+    src, rec = _two_step_case(shape, 3)
+    rng = np.random.default_rng(5)
+    sources = [(p, rng.standard_normal(T)) for p in src]
+    u0, um1 = _smooth(rng, shape), _smooth(rng, shape)
+    a = run_gpu(v, r, h, dt, T, "f32", sources=sources, receivers=rec, u0=u0, um1=um1, label="single")
+    b = run_gpu(v, r, h, dt, T, "f32", sources=sources, receivers=rec, u0=u0, um1=um1, two_step=config,
+                label="two-step")
+    for f in ("u", "u_prev", "traces"):
+        assert np.array_equal(a[f], b[f]), f
+
+
+def test_two_step_vs_oracle(oracle_mod):
+    shape, r, h, T = (40, 52, 90), 4, 10.0, 120
+    v = workloads.layered_velocity(shape, seed=23)
+    dt = 0.45 * oracle_mod.dt_max(3, r, h, v.max())
+    src, rec = (45, 26, 20), _receivers_3d(shape, 5)
+    got = run_gpu(v, r, h, dt, T, "f32", receivers=rec, ricker=(src, 30.0, 0.03), two_step=0, label="two-step")
+    ref = oracle_mod.forward(v, h, dt, r, T, [(src, oracle_mod.ricker(T, dt, 30.0, 0.03))], rec)
+    eu, et = rel_l2(got["u"], ref["u"]), rel_l2(got["traces"], ref["traces"])
+    say(f"two-step vs oracle: u {eu:.2e} traces {et:.2e}")
+    assert eu <= 1e-4 and et <= 1e-4
+
+
+def test_two_step_full_grid_bitwise(oracle_mod):
+    # the benchmark's 512^3 shot, 40 steps, both ways
+    shot = workloads.c2_3d_layered()
+    v = shot.velocity().astype(np.float32)
+    dt = shot.courant * oracle_mod.dt_max(3, shot.r, shot.h, float(v.max()))
+    T = 40
+    a = run_gpu(v, shot.r, shot.h, dt, T, "f32", receivers=shot.receivers, ricker=(shot.source, 60.0, 0.0),
+                label="512 single")
+    b = run_gpu(v, shot.r, shot.h, dt, T, "f32", receivers=shot.receivers, ricker=(shot.source, 60.0, 0.0),
+                two_step=0, label="512 two-step")
+    assert np.abs(a["u"]).max() > 0
+    for f in ("u", "u_prev", "traces"):
+        assert np.array_equal(a[f], b[f]), f
