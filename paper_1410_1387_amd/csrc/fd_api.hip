@@ -974,24 +974,38 @@ extern "C" int fd_batch_set(fd_batch *b, fd_ctx *const *ctxs, const int64_t *tar
     b->h_prefix.assign((size_t)nctx + 1, 0);
     // Re-chunk the members for the batch as a whole: the other shots supply parallelism,
     // so each shot can march longer z chunks (fewer prologue re-reads) than it would
-    // alone.  The cost model is that of choose_zch, summed over the members.
-    int zb = 0;
+    // alone.  For a target length Z every member takes c = ceil(nz / Z) chunks of equal
+    // length ceil(nz / c) <= Z (no short tail chunk); the launch costs about
+    // ceil(workgroups / slots) x (longest chunk + 2r) plane-times, minimised over the
+    // targets that are some member's exact chunk length.
+    std::vector<int64_t> zchm((size_t)nctx, 1);
     if (nctx > 0) {
         const int r = ctxs[0]->r, slots = ctxs[0]->slots;
-        static const int cand[] = {512, 384, 256, 192, 128, 96, 64, 48, 32, 24, 16};
+        std::vector<int64_t> cand;
+        for (int i = 0; i < nctx; ++i) {
+            const int64_t nz = ctxs[i]->L.knz;
+            for (int64_t c = 1; c <= std::max<int64_t>(1, nz / (2 * r)); ++c) cand.push_back((nz + c - 1) / c);
+        }
+        std::sort(cand.begin(), cand.end());
+        cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
         double best = 1e300;
-        for (int zc : cand) {
+        int64_t zt = cand.empty() ? 1 : cand.back();
+        for (int64_t Z : cand) {
             int64_t nwg = 0, planes = 0;
             for (int i = 0; i < nctx; ++i) {
-                const int64_t nz = ctxs[i]->L.knz, z = std::min<int64_t>(zc, nz);
-                nwg += ctxs[i]->tiles_x * ctxs[i]->tiles_y * ((nz + z - 1) / z);
-                planes = std::max<int64_t>(planes, z);
+                const int64_t nz = ctxs[i]->L.knz, cm = (nz + Z - 1) / Z, zm = (nz + cm - 1) / cm;
+                nwg += ctxs[i]->tiles_x * ctxs[i]->tiles_y * cm;
+                planes = std::max<int64_t>(planes, zm);
             }
             const double cost = (double)((nwg + slots - 1) / slots) * (double)(planes + 2 * r);
             if (cost < best - 1e-9) {
                 best = cost;
-                zb = zc;
+                zt = Z;
             }
+        }
+        for (int i = 0; i < nctx; ++i) {
+            const int64_t nz = ctxs[i]->L.knz, cm = (nz + zt - 1) / zt;
+            zchm[(size_t)i] = (nz + cm - 1) / cm;
         }
     }
     for (int i = 0; i < nctx; ++i) {
@@ -1000,7 +1014,7 @@ extern "C" int fd_batch_set(fd_batch *b, fd_ctx *const *ctxs, const int64_t *tar
         d.ctr[0] = c->step;
         d.ctr[1] = c->step;
         d.target = target[i];
-        d.zch = (int32_t)std::min<int64_t>(zb, c->L.knz);
+        d.zch = (int32_t)zchm[(size_t)i];
         d.chunks_z = (int32_t)((c->L.knz + d.zch - 1) / d.zch);
         b->h_desc[(size_t)i] = d;
         b->h_prefix[(size_t)i + 1] = b->h_prefix[(size_t)i] + (int32_t)(c->tiles_x * c->tiles_y * d.chunks_z);
