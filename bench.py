@@ -247,38 +247,52 @@ def summarize_prof(d: str, out_json: str = PROFILE_TRAFFIC):
         return out
 
     def counter(pattern, name):
+        """Counter value per kernel name, per dispatch (in dispatch order)."""
         vals = {}
         for r in rows(pattern):
             if r["Counter_Name"] == name:
-                vals.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
-        return {k: sum(v) / len(v) for k, v in vals.items()}
+                vals.setdefault(r["Kernel_Name"], []).append((int(r["Dispatch_Id"]), float(r["Counter_Value"])))
+        return {k: [x for _, x in sorted(v)] for k, v in vals.items()}
+
+    durations = {}
+    for r in rows("trace/*kernel_trace.csv"):
+        durations.setdefault(r["Kernel_Name"], []).append(
+            (int(r["Dispatch_Id"]), int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
+    durations = {k: [x for _, x in sorted(v)] for k, v in durations.items()}
+
+    def mean(xs):
+        return sum(xs) / len(xs)
 
     fetch = counter("fetch/*counter_collection.csv", "FETCH_SIZE")
     write = counter("write/*counter_collection.csv", "WRITE_SIZE")
     copy = [k for k in fetch if "copy_probe" in k][0]
     probe_bytes = 1 << 30
-    f_scale = probe_bytes / (fetch[copy] * 1024.0)
-    w_scale = probe_bytes / (write[copy] * 1024.0)
-    stats = {r["Name"]: r for r in rows("trace/*kernel_stats.csv")}
+    f_scale = probe_bytes / (mean(fetch[copy]) * 1024.0)
+    w_scale = probe_bytes / (mean(write[copy]) * 1024.0)
     cmds = [
         "rocprofv3 --kernel-trace --stats -d DIR/trace -o trace --output-format csv -- "
-        "python3 bench.py --steps 1 --warmup 0 --no-cpu --copy-probe",
+        "python3 bench.py --steps 1 --warmup 0 --no-cpu --gradient --copy-probe",
         "rocprofv3 --pmc FETCH_SIZE -d DIR/fetch -o fetch --output-format csv -- "
-        "python3 bench.py --steps 1 --warmup 0 --no-cpu --copy-probe",
+        "python3 bench.py --steps 1 --warmup 0 --no-cpu --gradient --copy-probe",
         "rocprofv3 --pmc WRITE_SIZE -d DIR/write -o write --output-format csv -- "
-        "python3 bench.py --steps 1 --warmup 0 --no-cpu --copy-probe",
+        "python3 bench.py --steps 1 --warmup 0 --no-cpu --gradient --copy-probe",
     ]
-    for tag, out_path, sources, algo in (("fwd_kernel", out_json, KERNEL_SOURCES, 16.0 * 512 ** 3),
-                                         ("vti_kernel", VTI_PROFILE_TRAFFIC, VTI_KERNEL_SOURCES, 36.0 * 512 ** 3),
-                                         ("adj_kernel", ADJ_PROFILE_TRAFFIC, ADJ_KERNEL_SOURCES, 28.0 * 256 ** 3)):
+    # (kernel, summary file, sources, algorithmic bytes, dispatches that belong to the
+    # workload: the 512^3 forward shot runs first, so its launches are the kernel's first
+    # 1000; the gradient section launches the same kernel at 256^3 afterwards)
+    for tag, out_path, sources, algo, first in (
+            ("fwd_kernel", out_json, KERNEL_SOURCES, 16.0 * 512 ** 3, 1000),
+            ("vti_kernel", VTI_PROFILE_TRAFFIC, VTI_KERNEL_SOURCES, 36.0 * 512 ** 3, None),
+            ("adj_kernel", ADJ_PROFILE_TRAFFIC, ADJ_KERNEL_SOURCES, 28.0 * 256 ** 3, None)):
         cands = [k for k in fetch if tag in k]
         if not cands:
             continue
-        kern = max(cands, key=lambda k: fetch[k])
-        avg_ns = float(stats[kern]["AverageNs"]) if kern in stats else None
-        fb, wb = fetch[kern] * 1024.0 * f_scale, write[kern] * 1024.0 * w_scale
+        kern = max(cands, key=lambda k: len(fetch[k]))
+        sel = slice(0, first)
+        avg_ns = mean(durations[kern][sel]) if kern in durations else None
+        fb, wb = mean(fetch[kern][sel]) * 1024.0 * f_scale, mean(write[kern][sel]) * 1024.0 * w_scale
         res = {
-            "kernel": kern, "kernel_hash": kernel_hash(sources),
+            "kernel": kern, "kernel_hash": kernel_hash(sources), "dispatches": len(fetch[kern][sel]),
             "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb, "hbm_bytes_per_launch": fb + wb,
             "algorithmic_bytes_per_launch": algo,
             "fetch_scale": f_scale, "write_scale": w_scale, "copy_probe_bytes": probe_bytes,
