@@ -35,28 +35,28 @@ static const FwdEntry k2_r4[] = {
     fwd_entry<TileCfg<float, 4, 2, 64, 1, 1>>("f32 r4 2d tile 256x1 (64 thr, 1 row/thr)"),
 };
 static const FwdEntry k3_r5[] = {
-    fwd_entry<TileCfg<float, 5, 3, 16, 16, 1>>("f32 r5 3d tile 64x16 (256 thr, 1 row/thr)"),
+    fwd_entry<TileCfg<float, 5, 3, 32, 16, 1>>("f32 r5 3d tile 128x16 (512 thr, 1 row/thr)"),
 };
 static const FwdEntry k2_r5[] = {
     fwd_entry<TileCfg<float, 5, 2, 64, 1, 1>>("f32 r5 2d tile 256x1 (64 thr, 1 row/thr)"),
 };
 static const FwdEntry k3_r6[] = {
-    fwd_entry<TileCfg<float, 6, 3, 16, 16, 1>>("f32 r6 3d tile 64x16 (256 thr, 1 row/thr)"),
+    fwd_entry<TileCfg<float, 6, 3, 32, 16, 1>>("f32 r6 3d tile 128x16 (512 thr, 1 row/thr)"),
 };
 static const FwdEntry k2_r6[] = {
     fwd_entry<TileCfg<float, 6, 2, 64, 1, 1>>("f32 r6 2d tile 256x1 (64 thr, 1 row/thr)"),
 };
 static const FwdEntry k3_r7[] = {
-    fwd_entry<TileCfg<float, 7, 3, 16, 16, 1>>("f32 r7 3d tile 64x16 (256 thr, 1 row/thr)"),
+    fwd_entry<TileCfg<float, 7, 3, 32, 16, 1>>("f32 r7 3d tile 128x16 (512 thr, 1 row/thr)"),
 };
 static const FwdEntry k2_r7[] = {
     fwd_entry<TileCfg<float, 7, 2, 64, 1, 1>>("f32 r7 2d tile 256x1 (64 thr, 1 row/thr)"),
 };
 static const FwdEntry k3_r8[] = {
+    fwd_entry<TileCfg<float, 8, 3, 32, 16, 1>>("f32 r8 3d tile 128x16 (512 thr, 1 row/thr)"),
     fwd_entry<TileCfg<float, 8, 3, 16, 16, 1>>("f32 r8 3d tile 64x16 (256 thr, 1 row/thr)"),
     fwd_entry<TileCfg<float, 8, 3, 32, 8, 1>>("f32 r8 3d tile 128x8 (256 thr, 1 row/thr)"),
     fwd_entry<TileCfg<float, 8, 3, 16, 32, 1>>("f32 r8 3d tile 64x32 (512 thr, 1 row/thr)"),
-    fwd_entry<TileCfg<float, 8, 3, 32, 16, 1>>("f32 r8 3d tile 128x16 (512 thr, 1 row/thr)"),
 };
 static const FwdEntry k2_r8[] = {
     fwd_entry<TileCfg<float, 8, 2, 64, 1, 1>>("f32 r8 2d tile 256x1 (64 thr, 1 row/thr)"),

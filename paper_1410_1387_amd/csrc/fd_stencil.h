@@ -4,10 +4,14 @@
 //     u^{n+1} = 2 u^n - u^{n-1} + c * Lh u^n + sources,   c = (v dt / h)^2,
 // where Lh = h^2 L is the radius-R star stencil applied on every axis (the xy
 // stencil form of Sec. 1 of Medina, St-Cyr and Warburton, extended to z with
-// the same radius and spacing).  It is evaluated in difference form,
+// the same radius and spacing).  For R <= 4 the forward evaluates it in
+// difference form,
 //     Lh u = sum_axes sum_l w_l [ (u_{+l} - u) + (u_{-l} - u) ],
-// which is algebraically the centre-weight form and keeps FP32 rounding of
-// smooth fields small.
+// algebraically the centre-weight form, which keeps FP32 rounding of smooth
+// fields small and costs nothing there (the kernel is bandwidth-bound).  For
+// R > 4 the vector work of that form limits the kernel, so it uses the
+// centre-weight form of the paper, ndim w_0 u + sum_axes sum_l w_l (u_{+l} + u_{-l}),
+// two operations per neighbour pair instead of four.
 //
 // Design (a star stencil is not a dense contraction, so no MFMA):
 //  - A workgroup owns a BX x BY tile of the xy plane and marches a chunk of z
@@ -468,18 +472,31 @@ __device__ __forceinline__ void fwd_tile(const ShotDesc &s, const typename C::ty
 #pragma unroll
                 for (int v = 0; v < VEC; ++v) {
                     const T u0 = q[ctr][e][v];
-                    T acc = T(0);
+                    T acc;
+                    if constexpr (R > 4) {
+                        acc = T(C::NDIM * W.w[0]) * u0;
 #pragma unroll
-                    for (int l = 1; l <= R; ++l)
-                        acc = fma_t(T(W.w[l]), (xs[C::LPAD + v + l] - u0) + (xs[C::LPAD + v - l] - u0), acc);
-                    if (C::NDIM == 3) {
+                        for (int l = 1; l <= R; ++l) acc = fma_t(T(W.w[l]), xs[C::LPAD + v + l] + xs[C::LPAD + v - l], acc);
+                        if (C::NDIM == 3) {
+#pragma unroll
+                            for (int l = 1; l <= R; ++l) acc = fma_t(T(W.w[l]), yr[HY + e + l][v] + yr[HY + e - l][v], acc);
+                        }
+#pragma unroll
+                        for (int l = 1; l <= R; ++l) acc = fma_t(T(W.w[l]), q[R + l][e][v] + q[R - l][e][v], acc);
+                    } else {
+                        acc = T(0);
 #pragma unroll
                         for (int l = 1; l <= R; ++l)
-                            acc = fma_t(T(W.w[l]), (yr[HY + e + l][v] - u0) + (yr[HY + e - l][v] - u0), acc);
-                    }
+                            acc = fma_t(T(W.w[l]), (xs[C::LPAD + v + l] - u0) + (xs[C::LPAD + v - l] - u0), acc);
+                        if (C::NDIM == 3) {
 #pragma unroll
-                    for (int l = 1; l <= R; ++l)
-                        acc = fma_t(T(W.w[l]), (q[R + l][e][v] - u0) + (q[R - l][e][v] - u0), acc);
+                            for (int l = 1; l <= R; ++l)
+                                acc = fma_t(T(W.w[l]), (yr[HY + e + l][v] - u0) + (yr[HY + e - l][v] - u0), acc);
+                        }
+#pragma unroll
+                        for (int l = 1; l <= R; ++l)
+                            acc = fma_t(T(W.w[l]), (q[R + l][e][v] - u0) + (q[R - l][e][v] - u0), acc);
+                    }
                     if (damp) {
                         const T G = gxy[e][v] * damp[s.nx + s.ny + z];
                         un[e][v] = G * fma_t(cv[cs][e][v], acc, T(2) * u0 - G * pv[cs][e][v]);

@@ -14,8 +14,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 
 # 3-D forward tile shapes.  Radii in SWEEP_RADII get every shape; others the default.
 F32_3D = [(16, 16, 2), (32, 8, 2), (16, 8, 4), (16, 32, 2), (32, 16, 2), (16, 16, 1), (8, 32, 2)]
-# radii above 4 keep one row per thread: two rows exceed 256 VGPRs and spill
-F32_3D_BIG_R = [(16, 16, 1), (32, 8, 1), (16, 32, 1), (32, 16, 1)]
+# radii above 4 keep one row per thread: two rows exceed 256 VGPRs and spill; 128x16
+# (512 threads) first: measured fastest at 384^3, r = 8
+F32_3D_BIG_R = [(32, 16, 1), (16, 16, 1), (32, 8, 1), (16, 32, 1)]
 F64_3D = [(32, 16, 1), (32, 8, 2), (16, 16, 2)]
 F32_SWEEP_RADII = {4, 8}
 F64_SWEEP_RADII = {4}

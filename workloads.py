@@ -54,7 +54,7 @@ def gaussian_smooth_periodic(f: np.ndarray, sigma: float) -> np.ndarray:
         shp = [1] * f.ndim
         shp[ax] = g.shape[0]
         mult = mult * g.reshape(shp)
-    return np.fft.irfftn(F * mult, s=f.shape)
+    return np.fft.irfftn(F * mult, s=f.shape, axes=tuple(range(f.ndim)))
 
 
 def smoothed_noise_velocity(shape, mean: float = 2500.0, std: float = 300.0, sigma: float = 8.0,
