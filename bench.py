@@ -278,17 +278,18 @@ def summarize_prof(d: str, out_json: str = PROFILE_TRAFFIC):
         "python3 bench.py --steps 1 --warmup 0 --no-cpu --gradient --copy-probe",
     ]
     # (kernel, summary file, sources, algorithmic bytes, dispatches that belong to the
-    # workload: the 512^3 forward shot runs first, so its launches are the kernel's first
-    # 1000; the gradient section launches the same kernel at 256^3 afterwards)
-    for tag, out_path, sources, algo, first in (
-            ("fwd_kernel", out_json, KERNEL_SOURCES, 16.0 * 512 ** 3, 1000),
-            ("vti_kernel", VTI_PROFILE_TRAFFIC, VTI_KERNEL_SOURCES, 36.0 * 512 ** 3, None),
-            ("adj_kernel", ADJ_PROFILE_TRAFFIC, ADJ_KERNEL_SOURCES, 28.0 * 256 ** 3, None)):
+    # measurement: the 512^3 forward shot runs first, so its launches are the forward
+    # kernel's first 1000 (the gradient section launches the same kernel at 256^3
+    # afterwards); the isolated adjoint launches that the bench times come last)
+    iso = ADJ_ISOLATED_WARMUP + ADJ_ISOLATED_REPS
+    for tag, out_path, sources, algo, sel in (
+            ("fwd_kernel", out_json, KERNEL_SOURCES, 16.0 * 512 ** 3, slice(0, 1000)),
+            ("vti_kernel", VTI_PROFILE_TRAFFIC, VTI_KERNEL_SOURCES, 36.0 * 512 ** 3, slice(0, None)),
+            ("adj_kernel", ADJ_PROFILE_TRAFFIC, ADJ_KERNEL_SOURCES, 28.0 * 256 ** 3, slice(-iso, None))):
         cands = [k for k in fetch if tag in k]
         if not cands:
             continue
         kern = max(cands, key=lambda k: len(fetch[k]))
-        sel = slice(0, first)
         avg_ns = mean(durations[kern][sel]) if kern in durations else None
         fb, wb = mean(fetch[kern][sel]) * 1024.0 * f_scale, mean(write[kern][sel]) * 1024.0 * w_scale
         res = {
@@ -406,7 +407,10 @@ def run_gradient():
     }
 
 
-def time_adjoint_kernel(v, case, dt, rec, reps=200):
+ADJ_ISOLATED_WARMUP, ADJ_ISOLATED_REPS = 5, 200
+
+
+def time_adjoint_kernel(v, case, dt, rec, reps=ADJ_ISOLATED_REPS):
     """Average duration of one adjoint-kernel launch at the gradient workload's size (read
     mu^{k+1}, mu^{k+2}, c, u^{k-1}, g; write mu^k, g: 28 B/pt): one-step segments need no
     recompute, so each fd_adjoint_segment call is exactly one adjoint launch."""
@@ -423,7 +427,7 @@ def time_adjoint_kernel(v, case, dt, rec, reps=200):
     u_cur, u_prev, mu, g = z(fb), z(fb), z(2 * fb), z(fb)
     resid = torch.zeros((case.nsteps, len(rec)), dtype=torch.float32, device=v.device)
     stream = torch.cuda.current_stream()
-    for k in range(5):
+    for k in range(ADJ_ISOLATED_WARMUP):
         F.fd_adjoint_segment(p.ctx, u_cur, u_prev, k, k + 1, None, mu, resid, 1.0, g)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
