@@ -233,6 +233,35 @@ def run_copy_probe(nbytes=1 << 30, reps=3):
     del a, b
 
 
+def run_stream_probe(nbytes=512 << 20, reps=20, blocks=(512, 768, 1024)):
+    """What HBM delivers for the forward update's stream mix (three reads and one in-place
+    write of nbytes each, 16-byte vectors, grid-stride) with no halo and no arithmetic:
+    the best of a few launch sizes, in GB/s, from HIP events on the launch stream."""
+    import torch
+
+    from paper_1410_1387_amd import fdwave as F
+
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.ones_like(a)
+    c = torch.ones_like(a)
+    stream = torch.cuda.current_stream()
+    sp = F.stream_ptr(stream)
+    best = 0.0
+    for nb in blocks:
+        for _ in range(3):
+            F.fd_stream_probe(a, b, c, nbytes, nb, sp)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            F.fd_stream_probe(a, b, c, nbytes, nb, sp)
+        e1.record(stream)
+        e1.synchronize()
+        best = max(best, 4.0 * nbytes / (e0.elapsed_time(e1) / reps * 1e-3) / 1e9)
+    del a, b, c
+    log(f"stream probe (3 reads + 1 in-place write, {nbytes >> 20} MiB each): {best:.0f} GB/s")
+    return best
+
+
 def summarize_prof(d: str, out_json: str = PROFILE_TRAFFIC):
     """Reduce a rocprofv3 directory (trace/, fetch/, write/ subdirectories of CSV output) to
     per-launch HBM bytes of the forward stencil kernel, scaled by the copy-probe factors."""
@@ -532,6 +561,9 @@ def main():
     if args.copy_probe:
         run_copy_probe()
     fw = run_forward(args)
+    stream_gbs = run_stream_probe()
+    fw["roofline"]["stream_probe_gbs"] = round(stream_gbs, 1)
+    fw["roofline"]["frac_of_stream_probe"] = round(fw["roofline"]["achieved"] / stream_gbs, 4)
     out = {
         "metric": "grid-point updates/s (Gpts/s), % of HBM roofline; p50/p99 shot latency",
         "value": round(fw["value"], 2),

@@ -276,6 +276,14 @@ int fd_batch_step(fd_batch *b, int64_t nsteps);
  * bytes must be a multiple of 16 and both pointers 16-byte aligned. */
 int fd_copy_probe(void *dst, const void *src, size_t bytes, void *stream);
 
+/* Streaming probe of the forward stencil's HBM mix without its halo or arithmetic: reads
+ * a, b and c (bytes each), writes c in place, on stream; grid-stride over 16-byte vectors
+ * with `blocks` workgroups of 256 threads (0 = 512).  What HBM delivers for the update's
+ * three reads and one write, the reference for the stencil's bandwidth fraction.  bytes
+ * must be a multiple of 16, all pointers 16-byte aligned (device memory, caller-owned);
+ * c is overwritten. */
+int fd_stream_probe(const void *a, const void *b, void *c, size_t bytes, int blocks, void *stream);
+
 /* Name of the stencil kernel configuration used for (dtype, r, ndim): tile shape,
  * z-chunk and launch size. */
 const char *fd_kernel_config(const fd_ctx *ctx);

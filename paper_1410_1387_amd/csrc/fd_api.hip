@@ -1106,3 +1106,14 @@ extern "C" int fd_copy_probe(void *dst, const void *src, size_t bytes, void *str
     if (e != hipSuccess) return fail(FD_E_DEVICE, "fd_copy_probe: %s", hipGetErrorString(e));
     return FD_OK;
 }
+
+extern "C" int fd_stream_probe(const void *a, const void *b, void *c, size_t bytes, int blocks, void *stream)
+{
+    if (!a || !b || !c || bytes % 16 != 0 || reinterpret_cast<uintptr_t>(a) % 16 ||
+        reinterpret_cast<uintptr_t>(b) % 16 || reinterpret_cast<uintptr_t>(c) % 16)
+        return fail(FD_E_INVAL, "fd_stream_probe: bad arguments");
+    if (blocks < 0 || blocks > 65536) return fail(FD_E_INVAL, "fd_stream_probe: blocks must be in [0, 65536]");
+    hipError_t e = launch_stream_probe(a, b, c, bytes, blocks == 0 ? 512 : blocks, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(FD_E_DEVICE, "fd_stream_probe: %s", hipGetErrorString(e));
+    return FD_OK;
+}

@@ -223,6 +223,28 @@ __global__ void copy_probe_kernel(f4 *__restrict__ dst, const f4 *__restrict__ s
         dst[i] = src[i];
 }
 
+// The forward stencil's stream mix without halo or stencil arithmetic: read a, b and c,
+// write c in place (as the update writes u^{n+1} over u^{n-1}); b and c nontemporal.
+// Grid-stride over 16-byte vectors, two vectors in flight per thread.
+__global__ __launch_bounds__(256) void stream_probe_kernel(const f4 *__restrict__ a, const f4 *__restrict__ b, f4 *c,
+                                                           int64_t n)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i0 < n; i0 += 2 * stride) {
+        f4 x[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int64_t i = i0 + u * stride;
+            if (i < n) x[u] = (a[i] + __builtin_nontemporal_load(&b[i])) * __builtin_nontemporal_load(&c[i]);
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int64_t i = i0 + u * stride;
+            if (i < n) __builtin_nontemporal_store(x[u], &c[i]);
+        }
+    }
+}
+
 }  // namespace
 
 template <typename T>
@@ -313,6 +335,15 @@ hipError_t launch_vti_prep(int dtype, const Geom &g, const void *vz, const void 
                            (const double *)eps, (const double *)delta, (double *)ax, (double *)an, (double *)az, k,
                            a, b, partial);
     hipLaunchKernelGGL(max3_final, dim3(1), dim3(kThreads), 0, st, (const double *)partial, nb, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_stream_probe(const void *a, const void *b, void *c, size_t bytes, int blocks, hipStream_t st)
+{
+    const int64_t n = (int64_t)(bytes / 16);
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(stream_probe_kernel, dim3(blocks), dim3(kThreads), 0, st, (const f4 *)a, (const f4 *)b, (f4 *)c,
+                       n);
     return hipGetLastError();
 }
 
