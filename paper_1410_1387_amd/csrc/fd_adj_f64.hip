@@ -4,13 +4,13 @@
 #include "fd_stencil.h"
 
 namespace fdw {
-static const AdjEntry a3_r1 = adj_entry<TileCfg<double, 1, 3, 32, 8, 1>>("f64 r1 3d tile 64x8 (256 thr, 1 row/thr)");
+static const AdjEntry a3_r1 = adj_entry<TileCfg<double, 1, 3, 32, 16, 1>>("f64 r1 3d tile 64x16 (512 thr, 1 row/thr)");
 static const AdjEntry a2_r1 = adj_entry<TileCfg<double, 1, 2, 64, 1, 1>>("f64 r1 2d tile 128x1 (64 thr, 1 row/thr)");
-static const AdjEntry a3_r2 = adj_entry<TileCfg<double, 2, 3, 32, 8, 1>>("f64 r2 3d tile 64x8 (256 thr, 1 row/thr)");
+static const AdjEntry a3_r2 = adj_entry<TileCfg<double, 2, 3, 32, 16, 1>>("f64 r2 3d tile 64x16 (512 thr, 1 row/thr)");
 static const AdjEntry a2_r2 = adj_entry<TileCfg<double, 2, 2, 64, 1, 1>>("f64 r2 2d tile 128x1 (64 thr, 1 row/thr)");
-static const AdjEntry a3_r3 = adj_entry<TileCfg<double, 3, 3, 32, 8, 1>>("f64 r3 3d tile 64x8 (256 thr, 1 row/thr)");
+static const AdjEntry a3_r3 = adj_entry<TileCfg<double, 3, 3, 32, 16, 1>>("f64 r3 3d tile 64x16 (512 thr, 1 row/thr)");
 static const AdjEntry a2_r3 = adj_entry<TileCfg<double, 3, 2, 64, 1, 1>>("f64 r3 2d tile 128x1 (64 thr, 1 row/thr)");
-static const AdjEntry a3_r4 = adj_entry<TileCfg<double, 4, 3, 32, 8, 1>>("f64 r4 3d tile 64x8 (256 thr, 1 row/thr)");
+static const AdjEntry a3_r4 = adj_entry<TileCfg<double, 4, 3, 32, 16, 1>>("f64 r4 3d tile 64x16 (512 thr, 1 row/thr)");
 static const AdjEntry a2_r4 = adj_entry<TileCfg<double, 4, 2, 64, 1, 1>>("f64 r4 2d tile 128x1 (64 thr, 1 row/thr)");
 static const AdjEntry a3_r5 = adj_entry<TileCfg<double, 5, 3, 32, 8, 1>>("f64 r5 3d tile 64x8 (256 thr, 1 row/thr)");
 static const AdjEntry a2_r5 = adj_entry<TileCfg<double, 5, 2, 64, 1, 1>>("f64 r5 2d tile 128x1 (64 thr, 1 row/thr)");

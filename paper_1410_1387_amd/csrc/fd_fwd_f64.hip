@@ -5,51 +5,53 @@
 
 namespace fdw {
 static const FwdEntry k3_r1[] = {
-    fwd_entry<TileCfg<double, 1, 3, 32, 16, 1>>("f64 r1 3d tile 64x16 (512 thr, 1 row/thr)"),
+    fwd_entry<TileCfg<double, 1, 3, 16, 16, 2>>("f64 r1 3d tile 32x32 (256 thr, 2 row/thr)"),
 };
 static const FwdEntry k2_r1[] = {
     fwd_entry<TileCfg<double, 1, 2, 64, 1, 1>>("f64 r1 2d tile 128x1 (64 thr, 1 row/thr)"),
 };
 static const FwdEntry k3_r2[] = {
-    fwd_entry<TileCfg<double, 2, 3, 32, 16, 1>>("f64 r2 3d tile 64x16 (512 thr, 1 row/thr)"),
+    fwd_entry<TileCfg<double, 2, 3, 16, 16, 2>>("f64 r2 3d tile 32x32 (256 thr, 2 row/thr)"),
 };
 static const FwdEntry k2_r2[] = {
     fwd_entry<TileCfg<double, 2, 2, 64, 1, 1>>("f64 r2 2d tile 128x1 (64 thr, 1 row/thr)"),
 };
 static const FwdEntry k3_r3[] = {
-    fwd_entry<TileCfg<double, 3, 3, 32, 16, 1>>("f64 r3 3d tile 64x16 (512 thr, 1 row/thr)"),
+    fwd_entry<TileCfg<double, 3, 3, 16, 16, 2>>("f64 r3 3d tile 32x32 (256 thr, 2 row/thr)"),
 };
 static const FwdEntry k2_r3[] = {
     fwd_entry<TileCfg<double, 3, 2, 64, 1, 1>>("f64 r3 2d tile 128x1 (64 thr, 1 row/thr)"),
 };
 static const FwdEntry k3_r4[] = {
+    fwd_entry<TileCfg<double, 4, 3, 16, 16, 2>>("f64 r4 3d tile 32x32 (256 thr, 2 row/thr)"),
     fwd_entry<TileCfg<double, 4, 3, 32, 16, 1>>("f64 r4 3d tile 64x16 (512 thr, 1 row/thr)"),
     fwd_entry<TileCfg<double, 4, 3, 32, 8, 2>>("f64 r4 3d tile 64x16 (256 thr, 2 row/thr)"),
-    fwd_entry<TileCfg<double, 4, 3, 16, 16, 2>>("f64 r4 3d tile 32x32 (256 thr, 2 row/thr)"),
 };
 static const FwdEntry k2_r4[] = {
     fwd_entry<TileCfg<double, 4, 2, 64, 1, 1>>("f64 r4 2d tile 128x1 (64 thr, 1 row/thr)"),
 };
 static const FwdEntry k3_r5[] = {
-    fwd_entry<TileCfg<double, 5, 3, 32, 16, 1>>("f64 r5 3d tile 64x16 (512 thr, 1 row/thr)"),
+    fwd_entry<TileCfg<double, 5, 3, 16, 16, 1>>("f64 r5 3d tile 32x16 (256 thr, 1 row/thr)"),
 };
 static const FwdEntry k2_r5[] = {
     fwd_entry<TileCfg<double, 5, 2, 64, 1, 1>>("f64 r5 2d tile 128x1 (64 thr, 1 row/thr)"),
 };
 static const FwdEntry k3_r6[] = {
-    fwd_entry<TileCfg<double, 6, 3, 32, 16, 1>>("f64 r6 3d tile 64x16 (512 thr, 1 row/thr)"),
+    fwd_entry<TileCfg<double, 6, 3, 16, 16, 1>>("f64 r6 3d tile 32x16 (256 thr, 1 row/thr)"),
 };
 static const FwdEntry k2_r6[] = {
     fwd_entry<TileCfg<double, 6, 2, 64, 1, 1>>("f64 r6 2d tile 128x1 (64 thr, 1 row/thr)"),
 };
 static const FwdEntry k3_r7[] = {
-    fwd_entry<TileCfg<double, 7, 3, 32, 16, 1>>("f64 r7 3d tile 64x16 (512 thr, 1 row/thr)"),
+    fwd_entry<TileCfg<double, 7, 3, 16, 16, 1>>("f64 r7 3d tile 32x16 (256 thr, 1 row/thr)"),
 };
 static const FwdEntry k2_r7[] = {
     fwd_entry<TileCfg<double, 7, 2, 64, 1, 1>>("f64 r7 2d tile 128x1 (64 thr, 1 row/thr)"),
 };
 static const FwdEntry k3_r8[] = {
+    fwd_entry<TileCfg<double, 8, 3, 16, 16, 1>>("f64 r8 3d tile 32x16 (256 thr, 1 row/thr)"),
     fwd_entry<TileCfg<double, 8, 3, 32, 16, 1>>("f64 r8 3d tile 64x16 (512 thr, 1 row/thr)"),
+    fwd_entry<TileCfg<double, 8, 3, 32, 8, 1>>("f64 r8 3d tile 64x8 (256 thr, 1 row/thr)"),
 };
 static const FwdEntry k2_r8[] = {
     fwd_entry<TileCfg<double, 8, 2, 64, 1, 1>>("f64 r8 2d tile 128x1 (64 thr, 1 row/thr)"),

@@ -17,13 +17,19 @@ F32_3D = [(16, 16, 2), (32, 8, 2), (16, 8, 4), (16, 32, 2), (32, 16, 2), (16, 16
 # radii above 4 keep one row per thread: two rows exceed 256 VGPRs and spill; 128x16
 # (512 threads) first: measured fastest at 384^3, r = 8
 F32_3D_BIG_R = [(32, 16, 1), (16, 16, 1), (32, 8, 1), (16, 32, 1)]
-F64_3D = [(32, 16, 1), (32, 8, 2), (16, 16, 2)]
+# FP64: 32x32 (two rows per thread) first for radii <= 4: 64x16 with 512 threads needs
+# 83 KB of LDS at r = 4, one workgroup per CU (512^3 r = 4: 174.6 vs 129.2 Gpts/s);
+# larger radii keep one row per thread (two rows spill at r >= 7); 32x16 measured fastest
+# at 384^3 r = 8 (116.5 vs 110.0 Gpts/s for 64x16)
+F64_3D = [(16, 16, 2), (32, 16, 1), (32, 8, 2)]
+F64_3D_BIG_R = [(16, 16, 1), (32, 16, 1), (32, 8, 1)]
 F32_SWEEP_RADII = {4, 8}
-F64_SWEEP_RADII = {4}
+F64_SWEEP_RADII = {4, 8}
 F2D = (64, 1, 1)          # 2-D forward and adjoint: one row of 64 threads
 ADJ_F32_3D = (32, 16, 1)        # radii <= 4 (measured 5-7 % faster than 64x16)
 ADJ_F32_3D_BIG_R = (16, 16, 1)  # radii > 4: two queues of 2r+2 planes need the smaller tile
-ADJ_F64_3D = (32, 8, 1)
+ADJ_F64_3D = (32, 16, 1)        # radii <= 4: 64x16, 512 threads (256^3: 176.0 vs 189.8 us for 64x8)
+ADJ_F64_3D_BIG_R = (32, 8, 1)
 # VTI kernel: (xy radius, z radius) pairs and tile shapes (threads along x, rows along y)
 VTI_RADII = [(2, 1), (2, 2), (4, 1), (4, 2), (4, 4), (8, 1), (8, 2), (8, 4), (8, 8),
              (12, 1), (12, 2), (12, 4), (12, 8)]
@@ -113,8 +119,8 @@ def vti_file(T, tiles):
 
 if __name__ == "__main__":
     fwd_file("float", F32_3D, F32_SWEEP_RADII, F32_3D_BIG_R)
-    fwd_file("double", F64_3D, F64_SWEEP_RADII)
+    fwd_file("double", F64_3D, F64_SWEEP_RADII, F64_3D_BIG_R)
     adj_file("float", ADJ_F32_3D, ADJ_F32_3D_BIG_R)
-    adj_file("double", ADJ_F64_3D)
+    adj_file("double", ADJ_F64_3D, ADJ_F64_3D_BIG_R)
     vti_file("float", VTI_F32)
     vti_file("double", VTI_F64)
