@@ -141,3 +141,29 @@ def test_vti_invalid_arguments_rejected(F):
     assert e.value.status == F.FD_E_RANGE
     ws = F.fd_vti_workspace_bytes((64, 64, 64), 12, 8, "f32", 1, 10)
     assert ws >= 7 * 64 ** 3 * 4
+
+
+def test_c_program_links_and_runs(F, oracle_mod, tmp_path):
+    # the boundary is usable from plain C: a C program that includes include/fdwave.h
+    # and links libfdwave.so gets the same weights, stability limit and sizes as the
+    # Python binding, and the error codes and messages of refused arguments
+    import shutil
+    import subprocess
+
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no C compiler")
+    exe = tmp_path / "c_abi_check"
+    libdir = os.path.dirname(F.LIB_PATH)
+    subprocess.run([gcc, "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"),
+                    os.path.join(ROOT, "tests", "c_abi_check.c"), "-L", libdir, "-lfdwave",
+                    "-Wl,-rpath," + libdir, "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    vals = dict(line.split(" ", 1) for line in out.strip().splitlines())
+    w = [float(x) for x in vals["w4"].split()]
+    assert w == list(F.fd_weights(4))
+    assert np.array_equal(np.array(w[1:]), oracle_mod.weights_f64(4)[1:])
+    assert float(vals["dtmax3_r4"]) == F.fd_dt_max(3, 4, 10.0, 4500.0)
+    assert int(vals["field_bytes"]) == F.fd_field_bytes((512, 512, 512), 4, "f32")
+    assert int(vals["workspace_bytes"]) == F.fd_workspace_bytes((512, 512, 512), 4, "f32", 1, 16384)
+    assert vals["bad_radius"] == f"{F.FD_E_INVAL} msg" and vals["bad_grid"] == f"{F.FD_E_INVAL} msg"
