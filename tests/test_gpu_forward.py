@@ -127,19 +127,19 @@ def test_fp32_long_run_layered(oracle_mod):
 # ----------------------------------------------------------------------------- full-size grids
 
 
-def _full_grid_case(oracle_mod, shot, T, seed):
+def _full_grid_case(oracle_mod, shot, T, seed, dtype="f32"):
     v = shot.velocity()
     dt = shot.courant * oracle_mod.dt_max(3, shot.r, shot.h, v.max())
     rng = np.random.default_rng(seed)
     u0 = _smooth(rng, shot.shape, 2)
     um1 = 0.99 * u0
-    got = run_gpu(v, shot.r, shot.h, dt, T, "f32", receivers=shot.receivers, u0=u0, um1=um1,
+    got = run_gpu(v, shot.r, shot.h, dt, T, dtype, receivers=shot.receivers, u0=u0, um1=um1,
                   ricker=(shot.source, shot.f0, 0.0), label=shot.name)
     ref = oracle_mod.forward(v, shot.h, dt, shot.r, T, [(shot.source, oracle_mod.ricker(T, dt, shot.f0, 0.0))],
                              shot.receivers, u0=u0, um1=um1)
     eu, et = rel_l2(got["u"], ref["u"]), rel_l2(got["traces"], ref["traces"])
-    say(f"{shot.name} x {T}: rel L2 u {eu:.2e} traces {et:.2e} [{got['config']}]")
-    assert eu <= 1e-4 and et <= 1e-4
+    say(f"{shot.name} {dtype} x {T}: rel L2 u {eu:.2e} traces {et:.2e} [{got['config']}]")
+    assert eu <= TOL[dtype] and et <= TOL[dtype]
 
 
 def test_full_grid_512_r4(oracle_mod):
@@ -149,6 +149,22 @@ def test_full_grid_512_r4(oracle_mod):
 
 def test_full_grid_384_r8(oracle_mod):
     _full_grid_case(oracle_mod, workloads.c3_3d_noise(), 16, 22)
+
+
+def test_full_grid_512_r4_fp64(oracle_mod):
+    # FP64 parity mode at the benchmark's size, in its default (32x32 tile) launch
+    _full_grid_case(oracle_mod, workloads.c2_3d_layered(), 8, 23, dtype="f64")
+
+
+@pytest.mark.parametrize("shape,r", [((130, 700, 1000), 4), ((97, 517, 1203), 8)])
+def test_large_ragged_grid(oracle_mod, shape, r):
+    # wide, ragged grids: partial tiles in x and y, several z chunks, a layered model,
+    # receivers on a plane and in a well; every point active from a random start
+    nz, ny, nx = shape
+    shot = workloads.Shot(f"3d_{nx}x{ny}x{nz}_r{r}_layered_fp32", 3, shape, 10.0, r, "f32", 0.5, 10,
+                          (nx // 3, ny // 2, nz // 4), receivers=_receivers_3d(shape, nz // 4),
+                          velocity_kind="layered", velocity_args={"seed": 5})
+    _full_grid_case(oracle_mod, shot, 10, 24)
 
 
 # ----------------------------------------------------------------------------- bitwise invariances
