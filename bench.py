@@ -11,7 +11,9 @@ stencil launches with the source and receivers fused in.  The velocity model is
 resident in HBM before the timed region starts.
 
     python bench.py [--steps K] [--warmup W] [--no-cpu] [--no-vti] [--gradient] [--serving] [--copy-probe]
-    python bench.py --summarize-prof DIR     # rocprofv3 CSVs -> profiles/ summary
+    python bench.py --workload 3d_384_r8_noise_fp32      # the other forward workloads (also
+    python bench.py --workload 3d_512_r4_layered_fp64    # 3d_512_r4_layered_fp32, the default)
+    python bench.py --summarize-prof DIR [--workload W]  # rocprofv3 CSVs -> profiles/ summary
 
 The JSON line also carries the paper's own benchmark kernel, the two-field VTI
 propagator (R_xy = 12, R_z = 8) on a 512^3 FP32 grid, under "vti".
@@ -41,6 +43,16 @@ ADJ_KERNEL_SOURCES = ["paper_1410_1387_amd/csrc/fd_stencil.h", "paper_1410_1387_
                       "paper_1410_1387_amd/csrc/fd_types.h"]
 VTI_KERNEL_SOURCES = ["paper_1410_1387_amd/csrc/fd_stencil.h", "paper_1410_1387_amd/csrc/fd_vti.h",
                       "paper_1410_1387_amd/csrc/fd_vti_f32.hip", "paper_1410_1387_amd/csrc/fd_types.h"]
+KERNEL_SOURCES_F64 = ["paper_1410_1387_amd/csrc/fd_stencil.h", "paper_1410_1387_amd/csrc/fd_fwd_f64.hip",
+                      "paper_1410_1387_amd/csrc/fd_types.h"]
+# forward workloads bench.py can time (--workload): name -> (traffic summary, kernel sources);
+# the first is the default and the only one the VTI, gradient and serving sections join
+FORWARD_WORKLOADS = {
+    "3d_512_r4_layered_fp32": (PROFILE_TRAFFIC, KERNEL_SOURCES),
+    "3d_384_r8_noise_fp32": (os.path.join(ROOT, "profiles", "fwd_r8_384_traffic.json"), KERNEL_SOURCES),
+    "3d_512_r4_layered_fp64": (os.path.join(ROOT, "profiles", "fwd_r4_512_fp64_traffic.json"), KERNEL_SOURCES_F64),
+}
+DEFAULT_WORKLOAD = "3d_512_r4_layered_fp32"
 # the paper's best VTI rates (Mpts/s, FP32, R_xy = 12, R_z = 8), quoted as context only
 PAPER_VTI_MPTS = {"K20x, OCCA:OpenCL, 2 pts/thread": 2525.0, "K10 (one chip), OCCA:CUDA, 2 pts/thread": 1579.0,
                   "2x Xeon (16 threads), OCCA:OpenMP": 1548.0}
@@ -74,28 +86,46 @@ def log(msg):
 # --------------------------------------------------------------------------- forward shot
 
 
+def forward_shot(name: str):
+    """The forward workload called `name` (see FORWARD_WORKLOADS)."""
+    import dataclasses
+
+    import workloads
+
+    if name == "3d_512_r4_layered_fp32":
+        return workloads.c2_3d_layered()
+    if name == "3d_384_r8_noise_fp32":
+        return workloads.c3_3d_noise()
+    if name == "3d_512_r4_layered_fp64":
+        return dataclasses.replace(workloads.c2_3d_layered(), name=name, dtype="f64")
+    raise ValueError(f"unknown workload {name}")
+
+
 def run_forward(args):
     import numpy as np
     import torch
 
-    import workloads
     from paper_1410_1387_amd import fdwave as F
 
-    shot = workloads.c2_3d_layered()
+    shot = forward_shot(args.workload)
+    traffic_json, sources = FORWARD_WORKLOADS[args.workload]
+    dtype = shot.dtype
+    tdt = torch.float32 if dtype == "f32" else torch.float64
+    esize = 4 if dtype == "f32" else 8
     nz, ny, nx = shot.shape
     T = shot.nsteps
-    v = torch.tensor(shot.velocity().astype(np.float32), device="cuda")
+    v = torch.tensor(shot.velocity(), dtype=tdt, device="cuda")
     vmax = float(v.max())
     dt = shot.courant * F.fd_dt_max(3, shot.r, shot.h, vmax)
     nrec = len(shot.receivers)
-    ws = torch.empty(F.fd_workspace_bytes(shot.shape, shot.r, "f32", 1, nrec), dtype=torch.uint8, device="cuda")
-    wav = torch.empty(T, dtype=torch.float32, device="cuda")
-    traces = torch.empty((T, nrec), dtype=torch.float32, device="cuda")
+    ws = torch.empty(F.fd_workspace_bytes(shot.shape, shot.r, dtype, 1, nrec), dtype=torch.uint8, device="cuda")
+    wav = torch.empty(T, dtype=tdt, device="cuda")
+    traces = torch.empty((T, nrec), dtype=tdt, device="cuda")
     stream = torch.cuda.current_stream()
     sp = F.stream_ptr(stream)
 
     def one_shot(ev=None):
-        ctx = F.fd_create(shot.shape, shot.r, shot.h, dt, v, "f32", "zero", ws, 1, nrec, sp)
+        ctx = F.fd_create(shot.shape, shot.r, shot.h, dt, v, dtype, "zero", ws, 1, nrec, sp)
         F.fd_ricker(wav, dt, shot.f0, 1.5 / shot.f0, sp)
         F.fd_inject(ctx, wav, shot.source, 1.0)
         F.fd_record(ctx, shot.receivers, traces, T)
@@ -122,18 +152,19 @@ def run_forward(args):
     launch_ms = sum(step_ms) / (args.steps * T)  # average stencil launch duration
     pts = nx * ny * nz
     value = pts * T * args.steps / wall / 1e9
-    algo_bytes = 16.0 * pts  # read u^n, u^{n-1}, c and write u^{n+1}, FP32
+    algo_bytes = 4.0 * esize * pts  # read u^n, u^{n-1}, c and write u^{n+1}
     achieved = algo_bytes / (launch_ms * 1e-3) / 1e9
-    tr = measured_traffic()
+    tr = measured_traffic(traffic_json, sources)
     finite = bool(torch.isfinite(traces).all().item())
     log(f"forward: {value:.1f} Gpts/s per shot incl. setup; stencil {launch_ms * 1e3:.1f} us/launch, "
         f"{achieved:.0f} GB/s algorithmic ({cfg}); traces finite={finite}")
     return {
         "value": value,
+        "dtype": dtype,
         "ms_per_step": wall / args.steps * 1e3,
         "config": {
             "workload": shot.name, "grid": [nx, ny, nz], "radius": shot.r, "h_m": shot.h, "dt_s": dt,
-            "time_steps_per_shot": T, "velocity": "8 layers U[1500,4500] m/s seed 0",
+            "time_steps_per_shot": T, "velocity": velocity_label(shot),
             "source": list(shot.source), "receivers": nrec, "shots_per_step": 1, "kernel": cfg,
         },
         "roofline": {
@@ -145,6 +176,15 @@ def run_forward(args):
             "stencil_gpts_per_s": round(pts / (launch_ms * 1e-3) / 1e9, 2),
         },
     }
+
+
+def velocity_label(shot) -> str:
+    a = shot.velocity_args
+    if shot.velocity_kind == "layered":
+        return f"8 layers U[1500,4500] m/s seed {a.get('seed', 0)}"
+    if shot.velocity_kind == "smoothed_noise":
+        return f"2500 m/s + smoothed noise (sigma 8 cells, std 300) seed {a.get('seed', 1)}"
+    return shot.velocity_kind
 
 
 def run_vti(args):
@@ -262,11 +302,15 @@ def run_stream_probe(nbytes=512 << 20, reps=20, blocks=(512, 768, 1024)):
     return best
 
 
-def summarize_prof(d: str, out_json: str = PROFILE_TRAFFIC):
+def summarize_prof(d: str, workload: str = DEFAULT_WORKLOAD):
     """Reduce a rocprofv3 directory (trace/, fetch/, write/ subdirectories of CSV output) to
-    per-launch HBM bytes of the forward stencil kernel, scaled by the copy-probe factors."""
+    per-launch HBM bytes of the stencil kernels, scaled by the copy-probe factors.  For the
+    default workload: the forward, VTI and adjoint kernels; otherwise that workload's
+    forward kernel."""
     import csv
     import glob
+
+    import numpy as np
 
     def rows(pattern):
         out = []
@@ -298,23 +342,26 @@ def summarize_prof(d: str, out_json: str = PROFILE_TRAFFIC):
     probe_bytes = 1 << 30
     f_scale = probe_bytes / (mean(fetch[copy]) * 1024.0)
     w_scale = probe_bytes / (mean(write[copy]) * 1024.0)
+    bench_args = ("--steps 1 --warmup 0 --no-cpu --gradient --copy-probe" if workload == DEFAULT_WORKLOAD else
+                  f"--workload {workload} --steps 1 --warmup 0 --no-cpu --no-vti --copy-probe")
     cmds = [
-        "rocprofv3 --kernel-trace --stats -d DIR/trace -o trace --output-format csv -- "
-        "python3 bench.py --steps 1 --warmup 0 --no-cpu --gradient --copy-probe",
-        "rocprofv3 --pmc FETCH_SIZE -d DIR/fetch -o fetch --output-format csv -- "
-        "python3 bench.py --steps 1 --warmup 0 --no-cpu --gradient --copy-probe",
-        "rocprofv3 --pmc WRITE_SIZE -d DIR/write -o write --output-format csv -- "
-        "python3 bench.py --steps 1 --warmup 0 --no-cpu --gradient --copy-probe",
+        f"rocprofv3 --kernel-trace --stats -d DIR/trace -o trace --output-format csv -- python3 bench.py {bench_args}",
+        f"rocprofv3 --pmc FETCH_SIZE -d DIR/fetch -o fetch --output-format csv -- python3 bench.py {bench_args}",
+        f"rocprofv3 --pmc WRITE_SIZE -d DIR/write -o write --output-format csv -- python3 bench.py {bench_args}",
     ]
     # (kernel, summary file, sources, algorithmic bytes, dispatches that belong to the
-    # measurement: the 512^3 forward shot runs first, so its launches are the forward
-    # kernel's first 1000 (the gradient section launches the same kernel at 256^3
-    # afterwards); the isolated adjoint launches that the bench times come last)
+    # measurement: the forward shot runs first, so its launches are the forward kernel's
+    # first T (the gradient section launches the same kernel at 256^3 afterwards); the
+    # isolated adjoint launches that the bench times come last)
     iso = ADJ_ISOLATED_WARMUP + ADJ_ISOLATED_REPS
-    for tag, out_path, sources, algo, sel in (
-            ("fwd_kernel", out_json, KERNEL_SOURCES, 16.0 * 512 ** 3, slice(0, 1000)),
-            ("vti_kernel", VTI_PROFILE_TRAFFIC, VTI_KERNEL_SOURCES, 36.0 * 512 ** 3, slice(0, None)),
-            ("adj_kernel", ADJ_PROFILE_TRAFFIC, ADJ_KERNEL_SOURCES, 28.0 * 256 ** 3, slice(-iso, None))):
+    shot = forward_shot(workload)
+    fwd_json, fwd_sources = FORWARD_WORKLOADS[workload]
+    esize = 4 if shot.dtype == "f32" else 8
+    sections = [("fwd_kernel", fwd_json, fwd_sources, 4.0 * esize * int(np.prod(shot.shape)), slice(0, shot.nsteps))]
+    if workload == DEFAULT_WORKLOAD:
+        sections += [("vti_kernel", VTI_PROFILE_TRAFFIC, VTI_KERNEL_SOURCES, 36.0 * 512 ** 3, slice(0, None)),
+                     ("adj_kernel", ADJ_PROFILE_TRAFFIC, ADJ_KERNEL_SOURCES, 28.0 * 256 ** 3, slice(-iso, None))]
+    for tag, out_path, sources, algo, sel in sections:
         cands = [k for k in fetch if tag in k]
         if not cands:
             continue
@@ -336,16 +383,15 @@ def summarize_prof(d: str, out_json: str = PROFILE_TRAFFIC):
 # --------------------------------------------------------------------------- CPU baseline
 
 
-def run_cpu_baseline(budget_s: float = 15.0):
+def run_cpu_baseline(workload: str = DEFAULT_WORKLOAD, budget_s: float = 15.0):
     """The FP64 oracle on the host cores, on a bounded sample of the same workload: the
-    full 512^3 grid and layered model, a few time steps (throughput per step is constant)."""
+    full grid and velocity model, a few time steps (throughput per step is constant)."""
     import numpy as np
 
     import oracle
-    import workloads
 
     oracle._lib()
-    shot = workloads.c2_3d_layered()
+    shot = forward_shot(workload)
     v = shot.velocity()
     dt = shot.courant * oracle.dt_max(3, shot.r, shot.h, v.max())
     # OpenMP threads the oracle runs with: OMP_NUM_THREADS if set, else one per usable core
@@ -366,10 +412,11 @@ def run_cpu_baseline(budget_s: float = 15.0):
     el = time.perf_counter() - t
     pts = int(np.prod(shot.shape))
     val = pts * nsteps / el / 1e9
-    log(f"cpu baseline: {val:.3f} Gpts/s ({nsteps} steps of 512^3 FP64 in {el:.1f} s, {cores} threads)")
+    grid = "x".join(str(n) for n in shot.shape[::-1])
+    log(f"cpu baseline: {val:.3f} Gpts/s ({nsteps} steps of {grid} FP64 in {el:.1f} s, {cores} threads)")
     return {"value": round(val, 4), "unit": "Gpts/s", "cores": cores, "kind": "oracle",
-            "sample": f"FP64 oracle, full 512^3 grid of the same layered workload, r=4, {nsteps} time steps "
-                      f"({el:.1f} s wall)"}
+            "sample": f"FP64 oracle, full {grid} grid of the same workload ({velocity_label(shot)}), r={shot.r}, "
+                      f"{nsteps} time steps ({el:.1f} s wall)"}
 
 
 def run_gradient():
@@ -531,7 +578,7 @@ def run_serving(nreq=256, budget_gib=96, sequential=True):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3, help="timed shots (each 1000 time steps of 512^3)")
+    ap.add_argument("--steps", type=int, default=3, help="timed shots (each a whole shot of the workload)")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--gradient", action="store_true", help="also time the adjoint gradient workload")
@@ -539,9 +586,12 @@ def main():
     ap.add_argument("--copy-probe", action="store_true", help="run a 1 GiB copy (counter scaling reference)")
     ap.add_argument("--no-vti", action="store_true", help="skip the VTI propagator section")
     ap.add_argument("--summarize-prof", metavar="DIR", help="summarize rocprofv3 CSV output and exit")
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(FORWARD_WORKLOADS),
+                    help="forward workload to time (the VTI, gradient and serving sections run only with "
+                         "the default)")
     args = ap.parse_args()
     if args.summarize_prof:
-        summarize_prof(args.summarize_prof)
+        summarize_prof(args.summarize_prof, args.workload)
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -575,18 +625,19 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": fw["dtype"],
         "data": "synthetic",
         "config": fw["config"],
         "roofline": fw["roofline"],
     }
-    if not args.no_vti:
+    default = args.workload == DEFAULT_WORKLOAD
+    if default and not args.no_vti:
         out["vti"] = run_vti(args)
-    if args.gradient:
+    if default and args.gradient:
         out["gradient"] = run_gradient()
-    if args.serving:
+    if default and args.serving:
         out["serving"] = run_serving()
-    out["cpu_baseline"] = None if args.no_cpu else run_cpu_baseline()
+    out["cpu_baseline"] = None if args.no_cpu else run_cpu_baseline(args.workload)
     print(json.dumps(out), flush=True)
 
 
