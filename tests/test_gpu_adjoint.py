@@ -97,6 +97,33 @@ def test_gradient_linear_in_residual(oracle_mod):
     assert float(torch.linalg.norm(g3 - 3.0 * g1) / torch.linalg.norm(3.0 * g1)) <= 1e-12
 
 
+@pytest.mark.parametrize("shape,r,T,K", [((16, 20, 24), 4, 60, 10), ((40, 50), 8, 120, 25)])
+def test_adjoint_dot_product(oracle_mod, shape, r, T, K):
+    # the transpose identity <F dv, dd> = <dv, F^T dd> for the Jacobian F of the traces
+    # with respect to v, in one random direction dv over every cell and random trace
+    # weights dd: F^T dd from the adjoint (autograd), F dv from central differences of
+    # the FP64 GPU forward (on the oracle this construction agrees to 7e-11 at eps = 1e-2)
+    import torch
+
+    from paper_1410_1387_amd.autograd import WaveProp
+
+    v, pb, _ = _problem(oracle_mod, shape, r, T, K, "f64", seed=7)
+    rng = np.random.default_rng(8)
+    dv = torch.tensor(rng.standard_normal(shape), device="cuda")
+    vt = torch.tensor(v, device="cuda").requires_grad_(True)
+    tr = WaveProp.apply(vt, pb)
+    dd = torch.tensor(rng.standard_normal(tuple(tr.shape)), device="cuda")
+    (ftd,) = torch.autograd.grad(tr, vt, dd)
+    rhs = float(torch.sum(dv * ftd))
+    eps = 1e-2
+    with torch.no_grad():
+        tp = WaveProp.apply(torch.tensor(v, device="cuda") + eps * dv, pb)
+        tm = WaveProp.apply(torch.tensor(v, device="cuda") - eps * dv, pb)
+    lhs = float(torch.sum((tp - tm) / (2 * eps) * dd))
+    say(f"dot product {shape} r={r}: <F dv, dd> {lhs:.12e}  <dv, F^T dd> {rhs:.12e}")
+    assert abs(lhs - rhs) <= 1e-8 * abs(rhs)
+
+
 # ----------------------------------------------------------------------------- full-size workload
 
 
