@@ -151,6 +151,52 @@ def test_full_grid_384_r8(oracle_mod):
     _full_grid_case(oracle_mod, workloads.c3_3d_noise(), 16, 22)
 
 
+def _energy(u1, u0, c, w):
+    """E^{n+1/2} = (u^{n+1} - u^n)^T C^-1 (u^{n+1} - u^n) - (u^{n+1})^T Lh u^n with Lh the
+    dimensionless stencil (zero outside the grid), C = (v dt / h)^2: constant in n for the
+    unforced leapfrog recursion, since Lh is symmetric (FP64, on the GPU, with torch)."""
+    import torch
+
+    r = len(w) - 1
+    up = torch.nn.functional.pad(u0, (r, r, r, r, r, r))
+    nz, ny, nx = u0.shape
+    lu = 3.0 * w[0] * u0
+    for l in range(1, r + 1):
+        lu = lu + w[l] * (up[r + l:r + l + nz, r:r + ny, r:r + nx] + up[r - l:r - l + nz, r:r + ny, r:r + nx]
+                          + up[r:r + nz, r + l:r + l + ny, r:r + nx] + up[r:r + nz, r - l:r - l + ny, r:r + nx]
+                          + up[r:r + nz, r:r + ny, r + l:r + l + nx] + up[r:r + nz, r:r + ny, r - l:r - l + nx])
+    d = u1 - u0
+    return float(torch.sum(d * d / c) - torch.sum(u1 * lu))
+
+
+def test_full_grid_energy_1000_steps(oracle_mod):
+    # the benchmark's shot (512^3, r = 4, FP32, layered, 1000 steps, its launch
+    # configuration): after the Ricker source has died out (step 500: its envelope is
+    # ~1e-27) the discrete energy must stay constant to the FP32 storage floor
+    import torch
+
+    from paper_1410_1387_amd import Propagator
+
+    shot = workloads.c2_3d_layered()
+    v = torch.tensor(shot.velocity(), dtype=torch.float64, device="cuda")
+    dt = shot.courant * oracle_mod.dt_max(3, shot.r, shot.h, float(v.max()))
+    c = (v * (dt / shot.h)) ** 2
+    w = [float(x) for x in oracle_mod.weights_f64(shot.r)]
+    p = Propagator(v.float(), shot.r, shot.h, dt, "f32", max_sources=1, max_receivers=len(shot.receivers))
+    p.inject(p.ricker(shot.nsteps, shot.f0), shot.source)
+    p.record(shot.receivers, shot.nsteps)
+    energies = []
+    for nsteps in (500, 250, 250):
+        p.step(nsteps)
+        u, up, n = p.state()
+        p.sync()
+        energies.append(_energy(u.double(), up.double(), c, w))
+        say(f"energy at step {n}: {energies[-1]:.12e} [{p.kernel_config}]")
+    p.close()
+    assert energies[0] > 0
+    assert max(abs(e - energies[0]) for e in energies) <= 1e-6 * energies[0]   # measured 1.1e-8
+
+
 def test_full_grid_512_r4_fp64(oracle_mod):
     # FP64 parity mode at the benchmark's size, in its default (32x32 tile) launch
     _full_grid_case(oracle_mod, workloads.c2_3d_layered(), 8, 23, dtype="f64")
