@@ -285,8 +285,9 @@ class ShotServer:
                     t_adm = time.perf_counter()
                     try:
                         ctx, tensors, traces, fp, npts = self._factory.create(req, sstream)
-                    except F.FdError as e:
-                        self._fail(req, arrival, fut, str(e))
+                    except Exception as e:  # a bad request fails alone; the others go on
+                        self._fail(req, arrival, fut, str(e) if isinstance(e, F.FdError) else
+                                   f"{type(e).__name__}: {e}")
                         continue
                     for t in tensors + [traces]:  # written by batched kernels on bstream
                         t.record_stream(bstream)
@@ -391,8 +392,9 @@ def run_sequential(requests: list, r: int = 4, dtype: str = "f32", realtime: boo
         start = now()
         try:
             ctx, tensors, traces, fp, npts = factory.create(req, stream)
-        except F.FdError as e:
-            out.append(ShotResult(req.rid, "failed", None, arrival, start, now(), 0, str(e)))
+        except Exception as e:
+            msg = str(e) if isinstance(e, F.FdError) else f"{type(e).__name__}: {e}"
+            out.append(ShotResult(req.rid, "failed", None, arrival, start, now(), 0, msg))
             continue
         F.fd_set_stream(ctx, F.stream_ptr(stream))
         F.fd_step(ctx, req.nsteps)

@@ -140,7 +140,7 @@ def test_server_budget_backpressure():
 
 
 def test_server_isolates_bad_requests():
-    from paper_1410_1387_amd.serving import ShotServer, ShotRequest
+    from paper_1410_1387_amd.serving import ShotRequest, ShotServer, run_sequential
 
     reqs = _requests(4, 7, spread=0.0)
     v = reqs[0].velocity
@@ -150,9 +150,17 @@ def test_server_isolates_bad_requests():
                             dt=4e-4))                                  # source outside the grid
     big = np.full((400, 400, 400), 2000.0, dtype=np.float32)
     reqs.append(ShotRequest(rid=92, velocity=big, nsteps=10, source=(1, 1, 1), receivers=reqs[0].receivers))
+    def broken_model():
+        raise ValueError("model file unreadable")
+
+    reqs.append(ShotRequest(rid=93, velocity=broken_model, shape=v.shape, nsteps=10, source=(1, 1, 1),
+                            receivers=reqs[0].receivers))              # the model cannot be built
     srv = ShotServer(r=4, chunk=8, max_shots=8, budget_bytes=1 << 30)  # 400^3 does not fit 1 GiB
     res = {r.rid: r for r in srv.serve_trace(reqs, realtime=False)}
     assert res[90].status == "failed" and "UNSTABLE" in res[90].error
     assert res[91].status == "failed" and "RANGE" in res[91].error
     assert res[92].status == "failed" and "budget" in res[92].error
+    assert res[93].status == "failed" and "ValueError" in res[93].error
     assert all(res[i].status == "ok" for i in range(4))
+    seq = {r.rid: r for r in run_sequential(reqs, realtime=False)}
+    assert seq[93].status == "failed" and all(seq[i].status == "ok" for i in range(4))
