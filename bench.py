@@ -490,10 +490,13 @@ def run_gradient():
 ADJ_ISOLATED_WARMUP, ADJ_ISOLATED_REPS = 5, 200
 
 
-def time_adjoint_kernel(v, case, dt, rec, reps=ADJ_ISOLATED_REPS):
+def time_adjoint_kernel(v, case, dt, rec, reps=ADJ_ISOLATED_REPS, nrot=8):
     """Average duration of one adjoint-kernel launch at the gradient workload's size (read
     mu^{k+1}, mu^{k+2}, c, u^{k-1}, g; write mu^k, g: 28 B/pt): one-step segments need no
-    recompute, so each fd_adjoint_segment call is exactly one adjoint launch."""
+    recompute, so each fd_adjoint_segment call is exactly one adjoint launch.  u^{k-1}
+    comes from `nrot` different fields in turn, as in the backward pass (where it is a new
+    ring slot every step): one field read again and again would be served by the
+    last-level cache and time the kernel faster than it runs in a gradient."""
     import torch
 
     from paper_1410_1387_amd import Propagator
@@ -504,15 +507,15 @@ def time_adjoint_kernel(v, case, dt, rec, reps=ADJ_ISOLATED_REPS):
     p.record(rec, case.nsteps)
     fb = p.field_bytes
     z = lambda nbytes: torch.zeros(nbytes // 4, dtype=torch.float32, device=v.device)  # noqa: E731
-    u_cur, u_prev, mu, g = z(fb), z(fb), z(2 * fb), z(fb)
+    u_curs, u_prev, mu, g = [z(fb) for _ in range(nrot)], z(fb), z(2 * fb), z(fb)
     resid = torch.zeros((case.nsteps, len(rec)), dtype=torch.float32, device=v.device)
     stream = torch.cuda.current_stream()
     for k in range(ADJ_ISOLATED_WARMUP):
-        F.fd_adjoint_segment(p.ctx, u_cur, u_prev, k, k + 1, None, mu, resid, 1.0, g)
+        F.fd_adjoint_segment(p.ctx, u_curs[k % nrot], u_prev, k, k + 1, None, mu, resid, 1.0, g)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     for k in range(reps):
-        F.fd_adjoint_segment(p.ctx, u_cur, u_prev, k + 1, k + 2, None, mu, resid, 1.0, g)
+        F.fd_adjoint_segment(p.ctx, u_curs[k % nrot], u_prev, k + 1, k + 2, None, mu, resid, 1.0, g)
     e1.record(stream)
     p.sync()
     ms = e0.elapsed_time(e1) / reps
