@@ -164,3 +164,43 @@ def test_server_isolates_bad_requests():
     assert all(res[i].status == "ok" for i in range(4))
     seq = {r.rid: r for r in run_sequential(reqs, realtime=False)}
     assert seq[93].status == "failed" and all(seq[i].status == "ok" for i in range(4))
+
+
+def test_server_real_sizes_alone_vs_mix_bitwise(oracle_mod):
+    # the serving workload's own requests (sides 128-400, layered models built on the GPU,
+    # surface receivers), with their step counts cut to 37-96 so the test stays short:
+    # batched with the default stepping window and graph chunks, every shot's traces are
+    # bitwise those of the same shot served alone
+    import dataclasses
+
+    import torch
+
+    from paper_1410_1387_amd import fdwave as F
+    from paper_1410_1387_amd.serving import ShotRequest, ShotServer, run_sequential
+
+    sides = {}
+    reqs = []
+    for q in workloads.serving_trace(24):
+        if q.n in sides and len(reqs) >= 5:
+            continue
+        sides[q.n] = True
+        prof = q.profile().astype("float32")
+        dt = 0.5 * F.fd_dt_max(3, 4, 10.0, float(prof.max()))
+
+        def make(prof=prof, n=q.n):
+            return torch.tensor(prof, device="cuda").view(n, 1, 1).expand(n, n, n).contiguous()
+
+        reqs.append(ShotRequest(rid=q.rid, velocity=make, shape=q.shape, nsteps=(37, 64, 96)[len(reqs) % 3],
+                                source=q.source, receivers=q.receivers(), dt=dt))
+        if len(reqs) == 7:
+            break
+    say("real sizes: " + ", ".join(f"{r.shape[0]}^3 x {r.nsteps}" for r in reqs))
+    assert {400, 128} <= {r.shape[0] for r in reqs}
+    seq = {r.rid: r for r in run_sequential(reqs, realtime=False)}
+    srv = ShotServer(r=4, budget_bytes=64 << 30, max_shots=8)
+    res = {r.rid: r for r in srv.serve_trace([dataclasses.replace(r, arrival=0.0) for r in reqs], realtime=False)}
+    say(f"stats {srv.stats}")
+    assert srv.stats["max_stepping_shots"] > 1
+    for rid in seq:
+        assert res[rid].status == "ok" and seq[rid].status == "ok"
+        assert np.array_equal(res[rid].traces.cpu().numpy(), seq[rid].traces.cpu().numpy()), rid
