@@ -196,6 +196,14 @@ int fd_sync(fd_ctx *ctx);
 /* Current step count (number of steps taken since step 0 or the last fd_set_state). */
 int fd_get_step(const fd_ctx *ctx, int64_t *step);
 
+/* Failure detection: *finite (host int) = 1 if every value of the current state u^n and
+ * u^{n-1} is finite, 0 if a NaN or an infinity has appeared (a corrupt source wavelet or
+ * state; the scheme itself stays bounded below fd_dt_max).  Reads both padded fields on
+ * the context's stream and synchronises it; a context stepped through an fd_batch must
+ * have its batch work completed first.  Not part of the method: a probe to run every
+ * so many steps. */
+int fd_check_finite(fd_ctx *ctx, int *finite);
+
 /* Copy the state (u^n, u^{n-1}) out of / into the context.
  *   layout FD_DENSE: device dense arrays of dtype (fd_get_state packs, fd_set_state
  *   unpacks and keeps the ghost cells zero); FD_PADDED: device buffers of

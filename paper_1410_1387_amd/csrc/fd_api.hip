@@ -754,6 +754,22 @@ extern "C" int fd_sync(fd_ctx *ctx)
     return FD_OK;
 }
 
+extern "C" int fd_check_finite(fd_ctx *ctx, int *finite)
+{
+    int st = check_ctx(ctx);
+    if (st) return st;
+    if (!finite) return fail(FD_E_INVAL, "fd_check_finite: null result pointer");
+    const int64_t n = (int64_t)(ctx->L.field_bytes / ctx->L.esize);
+    double *out = reinterpret_cast<double *>(ctx->ws + ctx->L.o_minmax);
+    HIP_TRY(ctx, launch_nonfinite((int)ctx->dtype, ctx->buf(0), ctx->buf(1), n,
+                                  reinterpret_cast<double *>(ctx->ws + ctx->L.o_partial), out, ctx->stream));
+    double flag[2] = {0.0, 0.0};
+    HIP_TRY(ctx, hipMemcpyAsync(flag, out, sizeof(flag), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    *finite = flag[1] == 0.0 ? 1 : 0;
+    return FD_OK;
+}
+
 extern "C" int fd_get_step(const fd_ctx *ctx, int64_t *step)
 {
     if (!ctx || !step) return fail(FD_E_INVAL, "fd_get_step: null argument");

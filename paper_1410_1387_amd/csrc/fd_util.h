@@ -24,6 +24,10 @@ hipError_t launch_ricker(int dtype, void *out, int64_t nsamp, double dt, double 
 hipError_t launch_grad_finish(int dtype, const Geom &g, const void *gpad, const void *v, void *out, double scale,
                               hipStream_t st);
 hipError_t launch_copy_probe(void *dst, const void *src, size_t bytes, hipStream_t st);
+// out[1] = 1 if a or b (n elements each) holds a non-finite value, else 0; partial holds
+// 2 * kPrepBlocks doubles.
+hipError_t launch_nonfinite(int dtype, const void *a, const void *b, int64_t n, double *partial, double *out,
+                           hipStream_t st);
 hipError_t launch_stream_probe(const void *a, const void *b, void *c, size_t bytes, int blocks, hipStream_t st);
 
 // VTI model preparation: from dense vz, eps, delta write ax, an, az = k nu^2 (k = dt^2/h^2)

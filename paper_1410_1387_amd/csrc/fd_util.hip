@@ -31,6 +31,28 @@ __device__ __forceinline__ int64_t padded_offset(const Geom &g, int64_t i)
     return g.off0 + z * g.pxy + y * g.px + x;
 }
 
+// Any non-finite value in two arrays of n elements: per block partial[2b] = 0,
+// partial[2b+1] = 1 if the block saw one (reduced by minmax_final).
+template <typename T>
+__global__ void nonfinite_kernel(const T *__restrict__ a, const T *__restrict__ b, int64_t n,
+                                 double *__restrict__ partial)
+{
+    __shared__ int sbad[kThreads];
+    int bad = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        if (!isfinite(a[i]) || !isfinite(b[i])) bad = 1;
+    sbad[threadIdx.x] = bad;
+    __syncthreads();
+    for (int s = kThreads / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sbad[threadIdx.x] = max(sbad[threadIdx.x], sbad[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partial[2 * blockIdx.x] = 0.0;
+        partial[2 * blockIdx.x + 1] = sbad[0] ? 1.0 : 0.0;
+    }
+}
+
 template <typename T>
 __global__ void prep_kernel(Geom g, const T *__restrict__ v, T *__restrict__ c, double k,
                             double *__restrict__ partial)
@@ -335,6 +357,20 @@ hipError_t launch_vti_prep(int dtype, const Geom &g, const void *vz, const void 
                            (const double *)eps, (const double *)delta, (double *)ax, (double *)an, (double *)az, k,
                            a, b, partial);
     hipLaunchKernelGGL(max3_final, dim3(1), dim3(kThreads), 0, st, (const double *)partial, nb, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_nonfinite(int dtype, const void *a, const void *b, int64_t n, double *partial, double *out,
+                           hipStream_t st)
+{
+    const int nb = blocks_for(n, kPrepBlocks);
+    if (dtype == 0)
+        hipLaunchKernelGGL(nonfinite_kernel<float>, dim3(nb), dim3(kThreads), 0, st, (const float *)a,
+                           (const float *)b, n, partial);
+    else
+        hipLaunchKernelGGL(nonfinite_kernel<double>, dim3(nb), dim3(kThreads), 0, st, (const double *)a,
+                           (const double *)b, n, partial);
+    hipLaunchKernelGGL(minmax_final, dim3(1), dim3(kThreads), 0, st, (const double *)partial, nb, out);
     return hipGetLastError();
 }
 

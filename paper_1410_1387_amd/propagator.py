@@ -118,6 +118,10 @@ class Propagator:
     def sync(self):
         F.fd_sync(self.ctx)
 
+    def check_finite(self) -> bool:
+        """True if the current state (u^n, u^{n-1}) holds no NaN or infinity (synchronises)."""
+        return F.fd_check_finite(self.ctx)
+
     @property
     def step_count(self) -> int:
         return F.fd_get_step(self.ctx)

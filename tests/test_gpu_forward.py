@@ -528,3 +528,41 @@ def test_two_step_full_grid_bitwise(oracle_mod):
     assert np.abs(a["u"]).max() > 0
     for f in ("u", "u_prev", "traces"):
         assert np.array_equal(a[f], b[f]), f
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_check_finite_probe(oracle_mod, dtype):
+    # the failure-detection probe: true on a clean run (and it leaves the run bitwise as
+    # it was), false once a NaN sample of a source wavelet has entered the wavefield
+    import torch
+
+    from paper_1410_1387_amd import Propagator
+
+    tdt = torch.float32 if dtype == "f32" else torch.float64
+    shape = (21, 30, 45)
+    v = torch.tensor(workloads.layered_velocity(shape, seed=8), dtype=tdt, device="cuda")
+    dt = 0.5 * oracle_mod.dt_max(3, 4, 10.0, float(v.max()))
+
+    def run(probe_at=None, nan_at=None):
+        p = Propagator(v, 4, 10.0, dt, dtype, max_sources=1)
+        wav = p.ricker(12, f0=30.0)
+        if nan_at is not None:
+            wav[nan_at] = float("nan")
+        p.inject(wav, (20, 15, 10))
+        flags = [p.check_finite()]
+        for n in (5, 7):
+            p.step(n)
+            if probe_at is None or p.step_count == probe_at:
+                flags.append(p.check_finite())
+        u, up, _ = p.state()
+        p.sync()
+        p.close()
+        return flags, u.cpu().numpy(), up.cpu().numpy()
+
+    f0, u0, up0 = run(probe_at=-1)          # no probe between the steps
+    f1, u1, up1 = run()                     # probe after step 5 and step 12
+    assert f0 == [True] and f1 == [True, True, True]
+    assert np.array_equal(u0, u1) and np.array_equal(up0, up1)
+    f2, _, _ = run(nan_at=7)                # NaN injected by the update producing u^8
+    say(f"{dtype}: clean {f1}, NaN at sample 7 {f2}")
+    assert f2 == [True, True, False]
