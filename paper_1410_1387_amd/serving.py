@@ -18,7 +18,9 @@
   roughly arrival order instead of all sharing the GPU at once (which would stretch
   every shot's latency without raising throughput);
 * after each chunk the loop retires shots whose counters reached their step count,
-  frees their memory and admits new ones at the next chunk boundary.
+  frees their memory and admits new ones at the next chunk boundary;
+* a request whose Future is cancelled before admission is dropped (once admitted it runs
+  to completion: its Future is then running and cannot be cancelled).
 
 Each shot's wavefields stay resident in HBM from admission to completion.  Results
 are the receiver traces; latency is completion minus arrival.  ``run_sequential``
@@ -222,20 +224,24 @@ class ShotServer:
             self._loop()
         except BaseException as e:  # surface to stop(); fail every waiting future
             self._error = e
-            for fut in list(self._outstanding):
-                if not fut.done():
-                    fut.set_exception(e)
+            pending = list(self._outstanding)
             while True:
                 try:
-                    _, _, fut = self._inbox.get_nowait()
+                    pending.append(self._inbox.get_nowait()[2])
                 except queue.Empty:
                     break
-                if not fut.done():
+            for fut in pending:
+                try:
                     fut.set_exception(e)
+                except cf.InvalidStateError:  # done or cancelled
+                    pass
 
     def _fail(self, req, arrival, fut, err: str):
         now = self.now()
-        fut.set_result(ShotResult(req.rid, "failed", None, arrival, now, now, 0, err))
+        try:
+            fut.set_result(ShotResult(req.rid, "failed", None, arrival, now, now, 0, err))
+        except cf.InvalidStateError:  # the caller cancelled it meanwhile
+            pass
         self._outstanding.discard(fut)
 
     def _loop(self):
@@ -269,6 +275,10 @@ class ShotServer:
                 # admit in arrival order while the head fits
                 while pending and len(active) < self.max_shots:
                     req, arrival, fut = pending[0]
+                    if fut.cancelled():  # cancelled while queued: drop it
+                        pending.popleft()
+                        self._outstanding.discard(fut)
+                        continue
                     try:
                         need = shot_footprint(req.grid_shape(), req.nsteps, len(req.receivers), self.r, self.dtype)
                     except Exception as e:  # malformed request
@@ -282,6 +292,9 @@ class ShotServer:
                     if used + need > self.budget:
                         break  # wait for memory: head-of-line order is kept
                     pending.popleft()
+                    if not fut.set_running_or_notify_cancel():  # cancelled just now
+                        self._outstanding.discard(fut)
+                        continue
                     t_adm = time.perf_counter()
                     try:
                         ctx, tensors, traces, fp, npts = self._factory.create(req, sstream)
@@ -339,8 +352,10 @@ class ShotServer:
         finally:
             self._retire_done(inflight, wait_all=True)
             for s in active:
-                if not s.future.done():
+                try:
                     s.future.set_exception(RuntimeError("server stopped"))
+                except cf.InvalidStateError:  # already completed
+                    pass
                 F.fd_destroy(s.ctx)
             F.fd_batch_destroy(batch)
 

@@ -204,3 +204,25 @@ def test_server_real_sizes_alone_vs_mix_bitwise(oracle_mod):
     for rid in seq:
         assert res[rid].status == "ok" and seq[rid].status == "ok"
         assert np.array_equal(res[rid].traces.cpu().numpy(), seq[rid].traces.cpu().numpy()), rid
+
+
+def test_server_cancellation():
+    # requests cancelled while queued are dropped; the others are served; a request that
+    # has been admitted can no longer be cancelled and completes
+    from paper_1410_1387_amd.serving import ShotServer
+
+    reqs = _requests(6, 11, sides=(32,), steps=(200, 200), spread=0.0)
+    need = 1 << 30
+    srv = ShotServer(r=4, chunk=8, max_shots=1, budget_bytes=need)   # one shot at a time
+    futs = [srv.submit(q) for q in reqs]
+    cancelled = [futs[i].cancel() for i in (3, 5)]
+    srv.start()
+    res = {}
+    for q, f in zip(reqs, futs):
+        if not f.cancelled():
+            res[q.rid] = f.result(timeout=120)
+    late = futs[0].cancel()                  # admitted (and finished) already
+    srv.stop()
+    say(f"cancelled {cancelled}, late cancel {late}, served {sorted(res)}")
+    assert all(cancelled) and not late
+    assert sorted(res) == [0, 1, 2, 4] and all(r.status == "ok" for r in res.values())
