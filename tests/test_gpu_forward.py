@@ -567,3 +567,40 @@ def test_check_finite_probe(oracle_mod, dtype):
     f2, _, _ = run(nan_at=7)                # NaN injected by the update producing u^8
     say(f"{dtype}: clean {f1}, NaN at sample 7 {f2}")
     assert f2 == [True, True, False]
+
+
+def _random_case(i):
+    """Seeded random forward case: 2-D or 3-D, any radius, sizes from 1 to a few tiles
+    (ragged), 1-3 sources with random wavelets, receivers anywhere (faces included), a
+    random initial state or none."""
+    rng = np.random.default_rng(1000 + i)
+    ndim = int(rng.choice([2, 3], p=[0.3, 0.7]))
+    r = int(rng.integers(1, 9))
+    if ndim == 3:
+        shape = tuple(int(x) for x in rng.integers(1, [40, 48, 150]))
+    else:
+        shape = tuple(int(x) for x in rng.integers(1, [90, 300]))
+    dtype = "f64" if i % 3 == 0 else "f32"
+    T = int(rng.integers(1, 30))
+    v = rng.uniform(1500.0, 4500.0, shape)
+    pos = lambda: tuple(int(rng.integers(0, n)) for n in shape[::-1])  # noqa: E731
+    sources = [(pos(), rng.standard_normal(T)) for _ in range(int(rng.integers(1, 4)))]
+    rec = np.array([pos() for _ in range(int(rng.integers(1, 40)))])
+    u0 = um1 = None
+    if rng.random() < 0.5:
+        u0 = rng.standard_normal(shape)
+        um1 = u0 + 0.01 * rng.standard_normal(shape)
+    return ndim, r, shape, dtype, T, v, sources, rec, u0, um1
+
+
+@pytest.mark.parametrize("i", range(24))
+def test_random_cases_vs_oracle(oracle_mod, i):
+    ndim, r, shape, dtype, T, v, sources, rec, u0, um1 = _random_case(i)
+    h = 10.0
+    dt = 0.5 * oracle_mod.dt_max(ndim, r, h, v.max())
+    got = run_gpu(v, r, h, dt, T, dtype, sources=sources, receivers=rec, u0=u0, um1=um1,
+                  label=f"random case {i}: r={r}")
+    ref = oracle_mod.forward(v, h, dt, r, T, sources, rec, u0=u0, um1=um1)
+    eu, et = rel_l2(got["u"], ref["u"]), rel_l2(got["traces"], ref["traces"])
+    say(f"  rel L2 u {eu:.2e} traces {et:.2e} [{got['config']}]")
+    assert got["step"] == T and eu <= TOL[dtype] and et <= TOL[dtype]
