@@ -197,3 +197,47 @@ def test_gradient_workload_256_fd():
     e64, ev = np.abs(g6 - fd).max() / scale, np.abs(gv - fd).max() / scale
     say(f"FD on 16 cells: FP64 gradient {e64:.2e}, FP32 adjoint (same residual) {ev:.2e} of max|FD|")
     assert scale > 0 and e64 <= 2e-4 and ev <= 1e-3
+
+
+def _random_adjoint_case(i):
+    """Seeded random gradient case: 2-D or 3-D, any radius, ragged sizes, random source and
+    receiver positions (faces included), a random checkpoint interval (1 to T)."""
+    from paper_1410_1387_amd.autograd import GradientProblem
+
+    rng = np.random.default_rng(3000 + i)
+    ndim = int(rng.choice([2, 3], p=[0.3, 0.7]))
+    r = int(rng.integers(1, 9))
+    shape = tuple(int(x) for x in (rng.integers(4, [20, 24, 30]) if ndim == 3 else rng.integers(4, [50, 70])))
+    T = int(rng.integers(5, 60))
+    K = int(rng.integers(1, T + 1))
+    h = 10.0
+    v = rng.uniform(1800.0, 3500.0, shape)
+    v_true = v * (1 + 0.05 * rng.standard_normal(shape))
+    dt = 0.5 * oracle_dt_max(ndim, r, h, max(v.max(), v_true.max()))
+    pos = lambda: tuple(int(rng.integers(0, n)) for n in shape[::-1])  # noqa: E731
+    src = pos()
+    rec = np.array([pos() for _ in range(int(rng.integers(1, 25)))])
+    dtype = "f64" if i % 2 == 0 else "f32"
+    pb = GradientProblem(r=r, h=h, dt=dt, nsteps=T, source=src, receivers=rec, f0=30.0, t0=0.04, ckpt=K,
+                         dtype=dtype)
+    return v, v_true, pb
+
+
+def oracle_dt_max(ndim, r, h, vmax):
+    import oracle
+
+    return oracle.dt_max(ndim, r, h, vmax)
+
+
+@pytest.mark.parametrize("i", range(12))
+def test_adjoint_random_cases_vs_oracle(oracle_mod, i):
+    v, v_true, pb = _random_adjoint_case(i)
+    wav = oracle_mod.ricker(pb.nsteps, pb.dt, pb.f0, pb.t0)
+    obs = oracle_mod.forward(v_true, pb.h, pb.dt, pb.r, pb.nsteps, [(pb.source, wav)], pb.receivers)["traces"]
+    say(f"random adjoint case {i}: shape={v.shape} r={pb.r} T={pb.nsteps} K={pb.ckpt} {pb.dtype}")
+    J, g = _gpu_gradient(v, pb, obs)
+    ref = oracle_mod.gradient(v, pb.h, pb.dt, pb.r, pb.nsteps, [(pb.source, wav)], pb.receivers, obs)
+    tol = 1e-9 if pb.dtype == "f64" else 1e-3
+    eg = rel_l2(g, ref["grad_v"])
+    say(f"  grad rel L2 {eg:.2e}, J {J:.6e} vs {ref['J']:.6e}")
+    assert eg <= tol and abs(J - ref["J"]) <= max(tol, 1e-6) * ref["J"]

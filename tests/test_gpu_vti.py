@@ -250,3 +250,42 @@ def test_vti_full_grid_sampled(oracle_mod):
             e = rel_l2(got[i][box][c], ref[f][c])
             assert e <= 1e-5, ((sx, sy, sz), f, e)
         say(f"  sample {(sx, sy, sz)} ok")
+
+
+_VTI_PAIRS = [(2, 1), (2, 2), (4, 1), (4, 2), (4, 4), (8, 1), (8, 2), (8, 4), (8, 8), (12, 1), (12, 2), (12, 4), (12, 8)]
+
+
+def _random_vti_case(i):
+    """Seeded random VTI case: any built radius pair, ragged sizes from 1 point, a z grid
+    stretched by a random factor, point-wise random eps and delta <= eps, 1-2 sources with
+    random (amp_p, amp_q), receivers anywhere, a random initial state or none."""
+    rng = np.random.default_rng(2000 + i)
+    rxy, rz = _VTI_PAIRS[i % len(_VTI_PAIRS)]
+    shape = tuple(int(x) for x in rng.integers(1, [30, 40, 110]))
+    dtype = "f64" if i % 4 == 0 else "f32"
+    T = int(rng.integers(1, 25))
+    h = 10.0
+    vz = rng.uniform(1500.0, 4000.0, shape)
+    eps = rng.uniform(0.0, 0.3, shape)
+    delta = eps * rng.uniform(0.0, 1.0, shape)
+    zc = workloads.stretched_z(shape[0], rz, h, float(rng.uniform(1.0, 2.0)))
+    pos = lambda: tuple(int(rng.integers(0, n)) for n in shape[::-1])  # noqa: E731
+    src = [(pos(), rng.standard_normal(T), float(rng.uniform(0, 1)), float(rng.uniform(0, 1)))
+           for _ in range(int(rng.integers(1, 3)))]
+    rec = np.array([pos() for _ in range(int(rng.integers(1, 30)))])
+    state = None
+    if rng.random() < 0.5:
+        p0 = rng.standard_normal(shape)
+        q0 = rng.standard_normal(shape)
+        state = (p0, p0 + 0.01 * rng.standard_normal(shape), q0, q0 + 0.01 * rng.standard_normal(shape))
+    return shape, rxy, rz, dtype, T, h, vz, eps, delta, zc, src, rec, state
+
+
+@pytest.mark.parametrize("i", range(16))
+def test_vti_random_cases_vs_oracle(oracle_mod, i):
+    shape, rxy, rz, dtype, T, h, vz, eps, delta, zc, src, rec, state = _random_vti_case(i)
+    dt = 0.6 * oracle_mod.vti_dt_max(rxy, rz, h, oracle_mod.z_weights(zc, rz), vz, eps, delta)
+    ref = oracle_mod.vti_forward(vz, eps, delta, h, dt, rxy, rz, T, zc=zc, sources=src, receivers=rec, state=state)
+    out = run_vti_gpu(vz, eps, delta, h, zc, dt, rxy, rz, T, dtype, sources=src, receivers=rec, state=state,
+                      label=f"random case {i}")
+    _compare(out, ref, 1e-4 if dtype == "f32" else 1e-11)
