@@ -226,3 +226,61 @@ def test_server_cancellation():
     say(f"cancelled {cancelled}, late cancel {late}, served {sorted(res)}")
     assert all(cancelled) and not late
     assert sorted(res) == [0, 1, 2, 4] and all(r.status == "ok" for r in res.values())
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_batch_random_mixes_bitwise(seed):
+    # random mixes of 2-6 shots (ragged 3-D sizes, different step counts and targets,
+    # random chunk lengths odd and even, membership changes mid-run): every shot's state
+    # and traces are bitwise those of the same shot stepped alone
+    import torch
+
+    from paper_1410_1387_amd import fdwave as F
+
+    rng = np.random.default_rng(50 + seed)
+    n = int(rng.integers(2, 7))
+    shots = []
+    for k in range(n):
+        shape = tuple(int(x) for x in rng.integers(3, [40, 50, 90]))
+        v = rng.uniform(1500.0, 4000.0, shape).astype(np.float32)
+        src = tuple(int(rng.integers(0, s)) for s in shape[::-1])
+        rec = np.array([tuple(int(rng.integers(0, s)) for s in shape[::-1]) for _ in range(int(rng.integers(1, 20)))])
+        shots.append((v, src, rec, int(rng.integers(5, 60))))
+    dt = 0.45 * F.fd_dt_max(3, 4, 10.0, 4000.0)
+    stream = torch.cuda.Stream()
+    alone = []
+    for (v, src, rec, T) in shots:
+        ctx, keep, tr = _make_ctx(v, src, rec, T, dt, stream)
+        F.fd_step(ctx, T)
+        u = torch.empty(v.shape, dtype=torch.float32, device="cuda")
+        F.fd_get_state(ctx, u, None)
+        F.fd_sync(ctx)
+        alone.append((u.cpu().numpy(), tr.cpu().numpy()))
+        F.fd_destroy(ctx)
+    ctxs = [_make_ctx(v, src, rec, T, dt, stream) for (v, src, rec, T) in shots]
+    bws = torch.empty(F.fd_batch_workspace_bytes(8), dtype=torch.uint8, device="cuda")
+    b = F.fd_batch_create(8, bws, F.stream_ptr(stream))
+    members = list(range(n))
+    first = members[: max(1, n // 2)]          # start with half, add the rest later
+    F.fd_batch_set(b, [ctxs[j][0] for j in first], [shots[j][3] for j in first])
+    steps = 0
+    while steps < 7:
+        c = int(rng.integers(1, 12))
+        F.fd_batch_step(b, c)
+        steps += c
+    F.fd_batch_set(b, [ctxs[j][0] for j in members], [shots[j][3] for j in members])
+    while any(F.fd_get_step(ctxs[j][0]) < shots[j][3] for j in members) and steps < 1000:
+        c = int(rng.integers(1, 12))
+        F.fd_batch_step(b, c)
+        steps += c
+    stream.synchronize()
+    say(f"mix of {n} shots, {steps} batched steps")
+    for j, (ctx, keep, tr) in enumerate(ctxs):
+        u = torch.empty(shots[j][0].shape, dtype=torch.float32, device="cuda")
+        F.fd_get_state(ctx, u, None)
+        F.fd_sync(ctx)
+        assert F.fd_get_step(ctx) == shots[j][3]
+        assert np.array_equal(u.cpu().numpy(), alone[j][0]), j
+        assert np.array_equal(tr.cpu().numpy(), alone[j][1]), j
+        F.fd_destroy(ctx)
+    F.fd_batch_destroy(b)
