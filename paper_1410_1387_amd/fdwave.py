@@ -60,6 +60,11 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() or "
                                "python paper_1410_1387_amd/build.py")
+        # torch ships its own HIP runtime; loading it first makes the library bind to that
+        # same runtime instance (loaded the other way round, the process ends up with a
+        # runtime that torch's device memory does not belong to and kernel calls fail)
+        import torch  # noqa: F401
+
         L = ctypes.CDLL(LIB_PATH)
         P, I32, I64, D, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
         pgrid = ctypes.POINTER(FdGrid)

@@ -604,3 +604,25 @@ def test_random_cases_vs_oracle(oracle_mod, i):
     eu, et = rel_l2(got["u"], ref["u"]), rel_l2(got["traces"], ref["traces"])
     say(f"  rel L2 u {eu:.2e} traces {et:.2e} [{got['config']}]")
     assert got["step"] == T and eu <= TOL[dtype] and et <= TOL[dtype]
+
+
+def test_library_loaded_before_torch():
+    # a program that calls the library (a host-only call) before it imports torch must
+    # still step on the GPU: the binding loads torch's HIP runtime first (fresh process)
+    import os
+    import subprocess
+    import sys
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_1410_1387_amd import fdwave as F\n"
+            "dt = 0.5 * F.fd_dt_max(3, 4, 10.0, 2000.0)\n"
+            "import torch\n"
+            "from paper_1410_1387_amd import Propagator\n"
+            "p = Propagator(torch.full((20, 24, 28), 2000.0, device='cuda'), 4, 10.0, dt, 'f32', max_sources=1)\n"
+            "p.inject(p.ricker(5, f0=30.0), (14, 12, 10))\n"
+            "p.step(5)\n"
+            "print('finite', p.check_finite())\n") % root
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    say(out.stdout.strip() + " " + out.stderr.strip()[-300:])
+    assert out.returncode == 0 and "finite True" in out.stdout
