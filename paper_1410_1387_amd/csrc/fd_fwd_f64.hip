@@ -26,6 +26,7 @@ static const FwdEntry k3_r4[] = {
     fwd_entry<TileCfg<double, 4, 3, 16, 16, 2>>("f64 r4 3d tile 32x32 (256 thr, 2 row/thr)"),
     fwd_entry<TileCfg<double, 4, 3, 32, 16, 1>>("f64 r4 3d tile 64x16 (512 thr, 1 row/thr)"),
     fwd_entry<TileCfg<double, 4, 3, 32, 8, 2>>("f64 r4 3d tile 64x16 (256 thr, 2 row/thr)"),
+    fwd_entry<TileCfg<double, 4, 3, 16, 16, 1>>("f64 r4 3d tile 32x16 (256 thr, 1 row/thr)"),
 };
 static const FwdEntry k2_r4[] = {
     fwd_entry<TileCfg<double, 4, 2, 64, 1, 1>>("f64 r4 2d tile 128x1 (64 thr, 1 row/thr)"),

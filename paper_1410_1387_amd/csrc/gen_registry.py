@@ -13,7 +13,10 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 # 3-D forward tile shapes.  Radii in SWEEP_RADII get every shape; others the default.
-F32_3D = [(16, 16, 2), (32, 8, 2), (16, 8, 4), (16, 32, 2), (32, 16, 2), (16, 16, 1), (8, 32, 2)]
+# 64x16 with one row per thread first: 138 VGPRs and 41 KB of LDS give three 256-thread
+# workgroups per CU, and at 512^3 r = 4 the chunker fills them with 768 workgroups of
+# 171 planes (352 Gpts/s against 342 for 64x32 with two rows per thread)
+F32_3D = [(16, 16, 1), (16, 16, 2), (32, 8, 2), (16, 8, 4), (16, 32, 2), (32, 16, 2), (8, 32, 2)]
 # radii above 4 keep one row per thread: two rows exceed 256 VGPRs and spill; 128x16
 # (512 threads) first: measured fastest at 384^3, r = 8
 F32_3D_BIG_R = [(32, 16, 1), (16, 16, 1), (32, 8, 1), (16, 32, 1)]
@@ -21,7 +24,7 @@ F32_3D_BIG_R = [(32, 16, 1), (16, 16, 1), (32, 8, 1), (16, 32, 1)]
 # 83 KB of LDS at r = 4, one workgroup per CU (512^3 r = 4: 174.6 vs 129.2 Gpts/s);
 # larger radii keep one row per thread (two rows spill at r >= 7); 32x16 measured fastest
 # at 384^3 r = 8 (116.5 vs 110.0 Gpts/s for 64x16)
-F64_3D = [(16, 16, 2), (32, 16, 1), (32, 8, 2)]
+F64_3D = [(16, 16, 2), (32, 16, 1), (32, 8, 2), (16, 16, 1)]
 F64_3D_BIG_R = [(16, 16, 1), (32, 16, 1), (32, 8, 1)]
 F32_SWEEP_RADII = {4, 8}
 F64_SWEEP_RADII = {4, 8}
