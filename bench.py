@@ -523,10 +523,15 @@ def time_adjoint_kernel(v, case, dt, rec, reps=ADJ_ISOLATED_REPS, nrot=8):
     return ms
 
 
-def serving_requests(nreq=256):
-    """The serving trace: Poisson arrivals at 20 req/s, cubic sides uniform in
-    {128, 192, 256, 320, 400}, 500-2000 steps, r = 4, FP32, layered velocity per request
-    seed.  The layered model is expanded on the GPU from its depth profile."""
+SERVING_SIDES = (128, 192, 256, 320, 400)
+SMALL_SIDES = (64, 96, 128, 160)
+
+
+def serving_requests(nreq=256, rate=20.0, sides=SERVING_SIDES):
+    """A serving trace: Poisson arrivals at ``rate`` req/s (20 for the main trace), cubic
+    sides uniform over ``sides`` ({128, 192, 256, 320, 400}), 500-2000 steps, r = 4, FP32,
+    layered velocity per request seed.  The layered model is expanded on the GPU from its
+    depth profile."""
     import torch
 
     import workloads
@@ -534,7 +539,7 @@ def serving_requests(nreq=256):
     from paper_1410_1387_amd.serving import ShotRequest
 
     reqs = []
-    for q in workloads.serving_trace(nreq):
+    for q in workloads.serving_trace(nreq, rate=rate, sides=sides):
         prof = q.profile().astype("float32")
         dt = 0.5 * F.fd_dt_max(3, 4, 10.0, float(prof.max()))
 
@@ -547,12 +552,11 @@ def serving_requests(nreq=256):
     return reqs
 
 
-def run_serving(nreq=256, budget_gib=96, sequential=True):
-    """Continuous batching of the serving trace, and the same trace served one shot at a
+def serve_both(reqs, budget_gib, sequential, label):
+    """One trace through the continuous-batching server, then (optionally) one shot at a
     time, on the same GPU."""
     from paper_1410_1387_amd.serving import ShotServer, run_sequential, summarize
 
-    reqs = serving_requests(nreq)
     srv = ShotServer(r=4, dtype="f32", budget_bytes=budget_gib << 30, max_shots=64, chunk=32)
     t0 = time.perf_counter()
     res = srv.serve_trace(reqs)
@@ -565,16 +569,28 @@ def run_serving(nreq=256, budget_gib=96, sequential=True):
                "batched_chunks": srv.stats["chunks"], "membership_changes": srv.stats["membership_changes"],
                "gpu_busy_s": round(srv.stats["gpu_busy_s"], 2), "host_admission_s": round(srv.stats["admit_s"], 2),
                "gpts_per_s_while_busy": round(srv.stats["chunk_points"] / max(srv.stats["gpu_busy_s"], 1e-9) / 1e9, 1)})
-    log(f"serving (continuous batching): {st['gpts_per_s']:.1f} Gpts/s, makespan {st['makespan_s']:.2f} s, "
+    log(f"serving {label} (continuous batching): {st['gpts_per_s']:.1f} Gpts/s, makespan {st['makespan_s']:.2f} s, "
         f"p50 {st['p50_latency_s']:.2f} s, p99 {st['p99_latency_s']:.2f} s, max resident {st['max_resident_shots']}")
-    out = {"workload": f"serving_{nreq}req_poisson20_sides128-400_r4_fp32", "batched": st}
+    out = {"batched": st}
     if sequential:
-        res1 = run_sequential(reqs)
-        s1 = summarize(res1)
-        log(f"serving (one at a time): {s1['gpts_per_s']:.1f} Gpts/s, makespan {s1['makespan_s']:.2f} s, "
+        s1 = summarize(run_sequential(reqs))
+        log(f"serving {label} (one at a time): {s1['gpts_per_s']:.1f} Gpts/s, makespan {s1['makespan_s']:.2f} s, "
             f"p50 {s1['p50_latency_s']:.2f} s, p99 {s1['p99_latency_s']:.2f} s")
         out["one_at_a_time"] = s1
         out["throughput_ratio"] = round(st["gpts_per_s"] / s1["gpts_per_s"], 3) if s1["gpts_per_s"] else None
+    return out
+
+
+def run_serving(nreq=256, budget_gib=96, sequential=True):
+    """The serving trace (sides 128-400 at 20 req/s), and a trace of small shots (sides
+    64-160, arriving at 400 req/s so that the GPU, not the arrivals, sets the pace), each
+    served with continuous batching and one shot at a time."""
+    out = {"workload": f"serving_{nreq}req_poisson20_sides128-400_r4_fp32"}
+    out.update(serve_both(serving_requests(nreq), budget_gib, sequential, "sides 128-400"))
+    small = {"workload": f"serving_{nreq}req_poisson400_sides64-160_r4_fp32"}
+    small.update(serve_both(serving_requests(nreq, rate=400.0, sides=SMALL_SIDES), budget_gib, sequential,
+                            "sides 64-160"))
+    out["small_shots"] = small
     return out
 
 
