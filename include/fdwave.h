@@ -184,7 +184,7 @@ int fd_step(fd_ctx *ctx, int64_t nsteps);
  * any remainder as single steps.  Periodic or damped contexts keep single steps.
  * config: index of the tile shape (0 = default).  aux = NULL disables.  On MI355X this
  * path moves 20 instead of 32 bytes per point and two steps but is latency-bound (one
- * workgroup per compute unit, two barriers per plane): 228 Gpts/s against 342 for single
+ * workgroup per compute unit, two barriers per plane): 228 Gpts/s against 351 for single
  * steps at 512^3, so it is off unless enabled.  Errors:
  * FD_E_INVAL (no two-step kernel: 3-D FP32 with r = 4 only; misaligned aux), FD_E_RANGE
  * (config), FD_E_NOMEM (aux too small). */
