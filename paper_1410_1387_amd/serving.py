@@ -16,7 +16,10 @@
   points per step reach ``fill_points``: enough work to fill the GPU (a small shot
   alone leaves most compute units idle), but no more, so that shots finish in
   roughly arrival order instead of all sharing the GPU at once (which would stretch
-  every shot's latency without raising throughput);
+  every shot's latency without raising throughput).  The default, 16 M points, is
+  about 190 MiB of FP32 fields (u^n, u^(n-1), c): a window of small shots then stays
+  within the GPU's 256 MB last-level cache, and a shot of 256^3 or more, which fills
+  the GPU by itself, steps alone;
 * after each chunk the loop retires shots whose counters reached their step count,
   frees their memory and admits new ones at the next chunk boundary;
 * a request whose Future is cancelled before admission is dropped (once admitted it runs
@@ -153,7 +156,7 @@ class ShotServer:
     """
 
     def __init__(self, r: int = 4, dtype: str = "f32", budget_bytes: int = 64 << 30, max_shots: int = 64,
-                 chunk: int = 32, device: str = "cuda", fill_points: Optional[int] = 160_000_000):
+                 chunk: int = 32, device: str = "cuda", fill_points: Optional[int] = 16_000_000):
         self.r, self.dtype = r, dtype
         self.budget, self.max_shots, self.chunk = int(budget_bytes), int(max_shots), int(chunk)
         self.fill_points = None if fill_points is None else int(fill_points)
