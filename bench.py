@@ -557,12 +557,12 @@ def serve_both(reqs, budget_gib, sequential, label):
     time, on the same GPU."""
     from paper_1410_1387_amd.serving import ShotServer, run_sequential, summarize
 
-    srv = ShotServer(r=4, dtype="f32", budget_bytes=budget_gib << 30, max_shots=64, chunk=32)
+    srv = ShotServer(r=4, dtype="f32", budget_bytes=budget_gib << 30, max_shots=64, chunk=16)
     t0 = time.perf_counter()
     res = srv.serve_trace(reqs)
     wall = time.perf_counter() - t0
     st = summarize(res)
-    st.update({"wall_s": round(wall, 2), "budget_gib": budget_gib, "chunk_steps": 32,
+    st.update({"wall_s": round(wall, 2), "budget_gib": budget_gib, "chunk_steps": 16,
                "max_resident_shots": srv.stats["max_resident_shots"], "fill_points": srv.fill_points,
                "max_stepping_shots": srv.stats["max_stepping_shots"],
                "max_resident_gib": round(srv.stats["max_resident_bytes"] / 2 ** 30, 2),

@@ -156,7 +156,7 @@ class ShotServer:
     """
 
     def __init__(self, r: int = 4, dtype: str = "f32", budget_bytes: int = 64 << 30, max_shots: int = 64,
-                 chunk: int = 32, device: str = "cuda", fill_points: Optional[int] = 16_000_000):
+                 chunk: int = 16, device: str = "cuda", fill_points: Optional[int] = 16_000_000):
         self.r, self.dtype = r, dtype
         self.budget, self.max_shots, self.chunk = int(budget_bytes), int(max_shots), int(chunk)
         self.fill_points = None if fill_points is None else int(fill_points)
