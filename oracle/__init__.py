@@ -114,11 +114,16 @@ def _lib():
             ctypes.c_int, P, ctypes.c_int, P, ctypes.c_double, ctypes.c_double, P, ctypes.c_int,
             I64, I64, P, P, P, P,
         ]
+        lib.fdo_adjoint_range.argtypes = [
+            ctypes.c_int, P, ctypes.c_int, P, ctypes.c_double, ctypes.c_double, P, ctypes.c_int,
+            I64, I64, I64, P, P, P, P, P, P,
+        ]
         lib.fdo_vti_forward.argtypes = [
             P, ctypes.c_int, ctypes.c_int, P, P, P, ctypes.c_double, ctypes.c_double, P, P, P, ctypes.c_int,
             ctypes.c_int, I64, I64, P, P, P, I64, P, P, P, P, P, P, P,
         ]
-        for f in (lib.fdo_laplacian, lib.fdo_forward, lib.fdo_adjoint, lib.fdo_vti_forward):
+        for f in (lib.fdo_laplacian, lib.fdo_forward, lib.fdo_adjoint, lib.fdo_adjoint_range,
+                  lib.fdo_vti_forward):
             f.restype = ctypes.c_int
         _lib_handle = lib
     return _lib_handle
@@ -339,33 +344,78 @@ def misfit(traces, observed) -> float:
     return 0.5 * float(np.sum(d * d))
 
 
-def gradient(v, h, dt, r, nsteps, sources, receivers, observed, periodic=False):
+def gradient(v, h, dt, r, nsteps, sources, receivers, observed, periodic=False, checkpoint=None, progress=None):
     """J and dJ/dv for J = 1/2 sum (traces - observed)^2 by the discrete adjoint.
 
-    Stores every forward state u^0..u^{T-1} (small grids only), runs the Lagrange
-    multiplier recursion in fd_oracle.c for dJ/dm (m = v^2), and returns
-    dJ/dv = 2 v dJ/dm.  Returns dict(J, grad_v, grad_m, traces).
+    Runs the Lagrange multiplier recursion in fd_oracle.c for dJ/dm (m = v^2) and returns
+    dJ/dv = 2 v dJ/dm.  The recursion at step k needs the forward state u^{k-1}:
+    checkpoint=None stores every state u^0..u^{T-1} (small grids only); checkpoint=K keeps
+    (u^{jK}, u^{jK-1}) for j = 0, 1, .. and, segment by segment from the last one,
+    recomputes u^{jK}..u^{jK+K-1} from its checkpoint before running the recursion over
+    that segment, so the memory is about T/K + K fields.  Both give the same numbers bit
+    for bit (the recomputed states are the stored ones).  Returns dict(J, grad_v, grad_m,
+    traces).
     """
     v = np.ascontiguousarray(v, dtype=np.float64)
     shape = v.shape
     ndim, n = _dims(shape)
-    fw = forward(v, h, dt, r, nsteps, sources, receivers, periodic=periodic, store_states=True)
-    resid = np.ascontiguousarray(fw["traces"] - np.asarray(observed, dtype=np.float64))
     rec_idx = linear_index(shape, receivers)
-    states = np.ascontiguousarray(fw["states"][:nsteps])
     m = np.ascontiguousarray(v * v)
     w = weights_f64(r)
+    obs = np.asarray(observed, dtype=np.float64)
     grad_m = np.zeros(shape, dtype=np.float64)
-    st = _lib().fdo_adjoint(
-        ndim, _ptr(n), r, _ptr(w), float(h), float(dt), _ptr(m), int(periodic), int(nsteps),
-        int(rec_idx.shape[0]), _ptr(rec_idx), _ptr(resid), _ptr(states), _ptr(grad_m),
-    )
-    _check(st, "adjoint")
+    if checkpoint is None:
+        fw = forward(v, h, dt, r, nsteps, sources, receivers, periodic=periodic, store_states=True)
+        traces = fw["traces"]
+        resid = np.ascontiguousarray(traces - obs)
+        states = np.ascontiguousarray(fw["states"][:nsteps])
+        st = _lib().fdo_adjoint(
+            ndim, _ptr(n), r, _ptr(w), float(h), float(dt), _ptr(m), int(periodic), int(nsteps),
+            int(rec_idx.shape[0]), _ptr(rec_idx), _ptr(resid), _ptr(states), _ptr(grad_m),
+        )
+        _check(st, "adjoint")
+    else:
+        K = int(checkpoint)
+        if K < 1:
+            raise ValueError("checkpoint interval must be >= 1")
+        sources = [(pos, np.asarray(wav, dtype=np.float64)) for pos, wav in sources]
+
+        def segment(k0, nst, u0, um1, store):
+            # the forward scheme from (u^{k0}, u^{k0-1}) for nst steps; source sample k0 + i
+            # enters step i
+            return forward(v, h, dt, r, nst, [(pos, wav[k0:]) for pos, wav in sources], receivers,
+                           periodic=periodic, u0=u0, um1=um1, store_states=store)
+
+        bounds = [(k, min(k + K, nsteps)) for k in range(0, nsteps, K)]
+        ckpts = []
+        traces = np.zeros((nsteps, rec_idx.shape[0]))
+        u, up = np.zeros(shape), np.zeros(shape)
+        for k_lo, k_hi in bounds:
+            ckpts.append((u, up))
+            fw = segment(k_lo, k_hi - k_lo, u, up, False)
+            traces[k_lo:k_hi] = fw["traces"]
+            u, up = fw["u"], fw["u_prev"]
+            if progress is not None:
+                progress(f"oracle gradient: forward to step {k_hi} of {nsteps}")
+        resid = np.ascontiguousarray(traces - obs)
+        lam1, lam2 = np.zeros(shape), np.zeros(shape)  # lambda^{T+1} = lambda^{T+2} = 0
+        for (k_lo, k_hi), (u0, um1) in zip(reversed(bounds), reversed(ckpts)):
+            # u^{k_lo} .. u^{k_hi-1}: the checkpoint and k_hi - k_lo - 1 recomputed steps
+            states = np.ascontiguousarray(segment(k_lo, k_hi - k_lo - 1, u0, um1, True)["states"])
+            st = _lib().fdo_adjoint_range(
+                ndim, _ptr(n), r, _ptr(w), float(h), float(dt), _ptr(m), int(periodic), int(k_hi), int(k_lo),
+                int(rec_idx.shape[0]), _ptr(rec_idx), _ptr(resid), _ptr(states), _ptr(lam1), _ptr(lam2),
+                _ptr(grad_m),
+            )
+            _check(st, "adjoint_range")
+            del states
+            if progress is not None:
+                progress(f"oracle gradient: adjoint down to step {k_lo}")
     return {
-        "J": misfit(fw["traces"], observed),
+        "J": misfit(traces, obs),
         "grad_m": grad_m,
         "grad_v": 2.0 * v * grad_m,
-        "traces": fw["traces"],
+        "traces": traces,
     }
 
 

@@ -182,16 +182,19 @@ int fdo_forward(int ndim, const int64_t *n, int r, const double *w, double h, do
     for (int64_t j = 0; j < nrec; ++j)
         if (rec_idx[j] < 0 || rec_idx[j] >= N) return FDO_EINVAL;
 
-    double *u_next = (double *)malloc((size_t)N * sizeof(double));
-    if (!u_next) return FDO_ENOMEM;
+    /* Three buffers whose roles rotate every step (u^{n+1} is written into the buffer that
+     * held u^{n-2}); the results are copied back into the caller's arrays at the end. */
+    double *spare = (double *)malloc((size_t)N * sizeof(double));
+    if (!spare) return FDO_ENOMEM;
+    double *cur = u_cur, *prev = u_prev, *next = spare;
     padded_t pf = {{0, 0, 0}, {0, 0, 0}, NULL};
     const double dt2 = dt * dt;
     const double src_scale = dt2 / pow(h, (double)ndim);
 
     if (states) memcpy(states, u_cur, (size_t)N * sizeof(double));
     for (int64_t step = 0; step < nsteps; ++step) {
-        if (pad_field(&g, u_cur, &pf)) {
-            free(u_next);
+        if (pad_field(&g, cur, &pf)) {
+            free(spare);
             return FDO_ENOMEM;
         }
 #pragma omp parallel for schedule(static)
@@ -201,21 +204,32 @@ int fdo_forward(int ndim, const int64_t *n, int r, const double *w, double h, do
                     int64_t p = (k * g.n[1] + j) * g.n[0] + i;
                     if (damp) {
                         const double G = damp[p];
-                        u_next[p] = G * (2.0 * u_cur[p] - G * u_prev[p] + dt2 * m[p] * laplacian_at(&g, &pf, i, j, k));
+                        next[p] = G * (2.0 * cur[p] - G * prev[p] + dt2 * m[p] * laplacian_at(&g, &pf, i, j, k));
                     } else {
-                        u_next[p] = 2.0 * u_cur[p] - u_prev[p] + dt2 * m[p] * laplacian_at(&g, &pf, i, j, k);
+                        next[p] = 2.0 * cur[p] - prev[p] + dt2 * m[p] * laplacian_at(&g, &pf, i, j, k);
                     }
                 }
         for (int64_t s = 0; s < nsrc; ++s)
-            u_next[src_idx[s]] += src_scale * src[step * nsrc + s];
+            next[src_idx[s]] += src_scale * src[step * nsrc + s];
         for (int64_t jr = 0; jr < nrec; ++jr)
-            traces[step * nrec + jr] = u_next[rec_idx[jr]];
+            traces[step * nrec + jr] = next[rec_idx[jr]];
         /* rotate: u^{n-1} <- u^n, u^n <- u^{n+1} */
-        memcpy(u_prev, u_cur, (size_t)N * sizeof(double));
-        memcpy(u_cur, u_next, (size_t)N * sizeof(double));
-        if (states) memcpy(states + (step + 1) * N, u_cur, (size_t)N * sizeof(double));
+        double *t = prev;
+        prev = cur;
+        cur = next;
+        next = t;
+        if (states) memcpy(states + (step + 1) * N, cur, (size_t)N * sizeof(double));
     }
-    free(u_next);
+    /* u^T and u^{T-1} back into the caller's arrays.  The buffers hold them in some
+     * rotation; `next` holds nothing needed, so the caller array it is gets filled first. */
+    if (next == u_prev) {
+        memcpy(u_prev, prev, (size_t)N * sizeof(double));
+        memcpy(u_cur, cur, (size_t)N * sizeof(double));
+    } else if (next == u_cur) {
+        memcpy(u_cur, cur, (size_t)N * sizeof(double));
+        memcpy(u_prev, prev, (size_t)N * sizeof(double));
+    }
+    free(spare);
     free(pf.data);
     return FDO_OK;
 }
@@ -228,38 +242,43 @@ int fdo_forward(int ndim, const int64_t *n, int r, const double *w, double h, do
  *     lambda^k = 2 lambda^{k+1} - lambda^{k+2} + dt^2 L( m lambda^{k+1} ) + sum_j resid[k-1][j] e_{x_j}
  *     dJ/dm   += dt^2 lambda^k (L u^{k-1})
  * L is symmetric for the zero and periodic boundaries, so L^T (m .) = L (m .).
+ *
+ * fdo_adjoint_range runs the recursion for k = k_hi down to k_lo + 1 only, so that the
+ * forward states can be recomputed segment by segment from checkpoints:
+ *   states_seg  [k_hi - k_lo][N]: u^{k_lo} .. u^{k_hi - 1}
+ *   lam1, lam2  in: lambda^{k_hi+1}, lambda^{k_hi+2};  out: lambda^{k_lo+1}, lambda^{k_lo+2}
+ *   grad_m      dJ/dm, accumulated (the caller zeroes it before the first range)
+ * fdo_adjoint is the whole range k = T .. 1 from zero multipliers:
  *   states   [nsteps][N]: u^0 .. u^{T-1} (as stored by fdo_forward)
  *   grad_m   out: dJ/dm per point (m = v^2)
  */
-int fdo_adjoint(int ndim, const int64_t *n, int r, const double *w, double h, double dt,
-                const double *m, int periodic, int64_t nsteps, int64_t nrec, const int64_t *rec_idx,
-                const double *resid, const double *states, double *grad_m)
+int fdo_adjoint_range(int ndim, const int64_t *n, int r, const double *w, double h, double dt,
+                      const double *m, int periodic, int64_t k_hi, int64_t k_lo, int64_t nrec,
+                      const int64_t *rec_idx, const double *resid, const double *states_seg,
+                      double *lam1_io, double *lam2_io, double *grad_m)
 {
     int st = check_grid(ndim, n, r, w, h);
     if (st) return st;
-    if (nsteps < 0 || nrec < 0 || !(dt > 0.0)) return FDO_EINVAL;
+    if (k_lo < 0 || k_hi < k_lo || nrec < 0 || !(dt > 0.0)) return FDO_EINVAL;
     grid_t g = make_grid(ndim, n, r, w, h, periodic);
     const int64_t N = npoints(&g);
     for (int64_t j = 0; j < nrec; ++j)
         if (rec_idx[j] < 0 || rec_idx[j] >= N) return FDO_EINVAL;
 
-    double *lam1 = (double *)calloc((size_t)N, sizeof(double)); /* lambda^{k+1} */
-    double *lam2 = (double *)calloc((size_t)N, sizeof(double)); /* lambda^{k+2} */
-    double *lam0 = (double *)calloc((size_t)N, sizeof(double)); /* lambda^k     */
-    double *mlam = (double *)calloc((size_t)N, sizeof(double)); /* m lambda^{k+1} */
-    if (!lam1 || !lam2 || !lam0 || !mlam) {
-        free(lam1);
-        free(lam2);
-        free(lam0);
+    double *spare = (double *)malloc((size_t)N * sizeof(double)); /* holds lambda^k */
+    double *mlam = (double *)malloc((size_t)N * sizeof(double));  /* m lambda^{k+1} */
+    if (!spare || !mlam) {
+        free(spare);
         free(mlam);
         return FDO_ENOMEM;
     }
+    double *lam1 = lam1_io, *lam2 = lam2_io, *lam0 = spare; /* lambda^{k+1}, lambda^{k+2}, lambda^k */
     const double dt2 = dt * dt;
-    memset(grad_m, 0, (size_t)N * sizeof(double));
     padded_t pf = {{0, 0, 0}, {0, 0, 0}, NULL};
     int status = FDO_OK;
 
-    for (int64_t k = nsteps; k >= 1; --k) {
+    for (int64_t k = k_hi; k >= k_lo + 1; --k) {
+#pragma omp parallel for schedule(static)
         for (int64_t p = 0; p < N; ++p) mlam[p] = m[p] * lam1[p];
         if (pad_field(&g, mlam, &pf)) {
             status = FDO_ENOMEM;
@@ -274,7 +293,7 @@ int fdo_adjoint(int ndim, const int64_t *n, int r, const double *w, double h, do
                 }
         for (int64_t jr = 0; jr < nrec; ++jr)
             lam0[rec_idx[jr]] += resid[(k - 1) * nrec + jr];
-        const double *u_km1 = states + (k - 1) * N;
+        const double *u_km1 = states_seg + (k - 1 - k_lo) * N;
         if (pad_field(&g, u_km1, &pf)) {
             status = FDO_ENOMEM;
             break;
@@ -292,10 +311,41 @@ int fdo_adjoint(int ndim, const int64_t *n, int r, const double *w, double h, do
         lam1 = lam0;
         lam0 = t;
     }
-    free(lam1);
-    free(lam2);
-    free(lam0);
+    /* the two newest multipliers back into the caller's arrays; lam0 holds nothing needed,
+     * so the caller array it is gets filled first */
+    if (lam0 == lam2_io) {
+        memcpy(lam2_io, lam2, (size_t)N * sizeof(double));
+        memcpy(lam1_io, lam1, (size_t)N * sizeof(double));
+    } else if (lam0 == lam1_io) {
+        memcpy(lam1_io, lam1, (size_t)N * sizeof(double));
+        memcpy(lam2_io, lam2, (size_t)N * sizeof(double));
+    }
+    free(spare);
     free(mlam);
     free(pf.data);
     return status;
+}
+
+int fdo_adjoint(int ndim, const int64_t *n, int r, const double *w, double h, double dt,
+                const double *m, int periodic, int64_t nsteps, int64_t nrec, const int64_t *rec_idx,
+                const double *resid, const double *states, double *grad_m)
+{
+    int st = check_grid(ndim, n, r, w, h);
+    if (st) return st;
+    if (nsteps < 0) return FDO_EINVAL;
+    grid_t g = make_grid(ndim, n, r, w, h, periodic);
+    const int64_t N = npoints(&g);
+    double *lam1 = (double *)calloc((size_t)N, sizeof(double)); /* lambda^{T+1} = 0 */
+    double *lam2 = (double *)calloc((size_t)N, sizeof(double)); /* lambda^{T+2} = 0 */
+    if (!lam1 || !lam2) {
+        free(lam1);
+        free(lam2);
+        return FDO_ENOMEM;
+    }
+    memset(grad_m, 0, (size_t)N * sizeof(double));
+    st = fdo_adjoint_range(ndim, n, r, w, h, dt, m, periodic, nsteps, 0, nrec, rec_idx, resid, states, lam1,
+                           lam2, grad_m);
+    free(lam1);
+    free(lam2);
+    return st;
 }

@@ -78,3 +78,37 @@ def test_gradient_is_linear_in_residual(oracle_mod):
     obs2 = fw - 2.0 * (fw - obs)
     g2 = oracle_mod.gradient(v, h, dt, r, T, src, rec, obs2)["grad_v"]
     assert np.abs(g2 - 2.0 * g1).max() <= 1e-13 * np.abs(g1).max()
+
+
+@pytest.mark.parametrize("shape,r,T", [((14, 17), 2, 61), ((7, 9, 11), 4, 37)])
+def test_checkpointed_gradient_equals_store_all(oracle_mod, shape, r, T):
+    # recomputing each segment from its checkpoint repeats the forward arithmetic, and the
+    # multiplier recursion carried across segments is the same recursion: the gradient,
+    # the misfit and the traces are bit for bit those of the path that stores every state,
+    # for intervals that divide T, that do not, of one step, and longer than the run
+    rng, v, h, dt, src, rec, obs = _setup(shape, r, T, 15)
+    ref = oracle_mod.gradient(v, h, dt, r, T, src, rec, obs)
+    seen = []
+    for K in (1, 5, T // 3, T - 1, T, T + 7):
+        g = oracle_mod.gradient(v, h, dt, r, T, src, rec, obs, checkpoint=K, progress=seen.append)
+        assert np.array_equal(g["grad_v"], ref["grad_v"]), K
+        assert np.array_equal(g["traces"], ref["traces"]) and g["J"] == ref["J"], K
+    assert seen and np.abs(ref["grad_v"]).max() > 0
+
+
+def test_checkpointed_gradient_central_fd(oracle_mod):
+    # the checkpointed path against central differences of the misfit directly (not only
+    # through the store-all path)
+    shape, r, T = (10, 12, 13), 3, 45
+    rng, v, h, dt, src, rec, obs = _setup(shape, r, T, 16)
+    gv = oracle_mod.gradient(v, h, dt, r, T, src, rec, obs, checkpoint=8)["grad_v"]
+    scale = np.abs(gv).max()
+    for f in rng.choice(v.size, size=4, replace=False):
+        idx = np.unravel_index(f, v.shape)
+        eps = 1e-3 * v[idx]
+        vp, vm = v.copy(), v.copy()
+        vp[idx] += eps
+        vm[idx] -= eps
+        Jp = oracle_mod.misfit(oracle_mod.forward(vp, h, dt, r, T, src, rec)["traces"], obs)
+        Jm = oracle_mod.misfit(oracle_mod.forward(vm, h, dt, r, T, src, rec)["traces"], obs)
+        assert abs((Jp - Jm) / (2 * eps) - gv[idx]) <= 1e-6 * scale
