@@ -70,3 +70,19 @@ def run_gpu(v, r, h, dt, T, dtype="f32", sources=(), receivers=None, bc="zero", 
     }
     p.close()
     return out
+
+
+def oracle_forward_chunked(oracle_mod, v, h, dt, r, T, sources, receivers, say, chunk=100, what="oracle"):
+    """oracle.forward over T steps in chunks of `chunk` steps, each starting from the
+    previous chunk's (u, u_prev); source sample k0 + i enters step i of the chunk, so the
+    result is the one-call result bit for bit."""
+    u = up = None
+    traces = []
+    for k0 in range(0, T, chunk):
+        k1 = min(T, k0 + chunk)
+        fw = oracle_mod.forward(v, h, dt, r, k1 - k0, [(pos, np.asarray(wav)[k0:]) for pos, wav in sources],
+                                receivers, u0=u, um1=up)
+        u, up = fw["u"], fw["u_prev"]
+        traces.append(fw["traces"])
+        say(f"{what}: step {k1} of {T}")
+    return {"u": u, "u_prev": up, "traces": np.concatenate(traces, axis=0)}

@@ -226,3 +226,21 @@ def test_source_scaling_and_time_level(oracle_mod):
     assert u1[5, 4, 3] == dt * dt / h ** 3
     assert np.count_nonzero(u1) == 1
     assert out["traces"][0, 0] == dt * dt / h ** 3 and out["traces"][0, 1] == 0.0
+
+
+def test_chunked_forward_bitwise(oracle_mod):
+    # a run split into chunks, each restarted from the previous chunk's (u, u_prev) with
+    # the wavelet shifted, is the one-call run bit for bit (how the full-size parity tests
+    # run the oracle)
+    from gpu_util import oracle_forward_chunked
+
+    shape, r, h, T = (9, 11, 13), 3, 10.0, 37
+    v = 1800.0 + 900.0 * np.random.default_rng(5).random(shape)
+    dt = 0.5 * oracle_mod.dt_max(3, r, h, v.max())
+    src = [((6, 5, 4), oracle_mod.ricker(T, dt, 40.0, 0.03)), ((0, 10, 8), np.random.default_rng(6).random(T))]
+    rec = np.array([(1, 2, 3), (12, 10, 8), (6, 5, 4)])
+    one = oracle_mod.forward(v, h, dt, r, T, src, rec)
+    for chunk in (1, 5, 36, 40):
+        got = oracle_forward_chunked(oracle_mod, v, h, dt, r, T, src, rec, lambda m: None, chunk=chunk)
+        for key in ("u", "u_prev", "traces"):
+            assert np.array_equal(got[key], one[key]), (chunk, key)
