@@ -199,9 +199,9 @@ int fd_get_step(const fd_ctx *ctx, int64_t *step);
 /* Failure detection: *finite (host int) = 1 if every value of the current state u^n and
  * u^{n-1} is finite, 0 if a NaN or an infinity has appeared (a corrupt source wavelet or
  * state; the scheme itself stays bounded below fd_dt_max).  Reads both padded fields on
- * the context's stream and synchronises it; a context stepped through an fd_batch must
- * have its batch work completed first.  Not part of the method: a probe to run every
- * so many steps. */
+ * the context's stream and synchronises it (batched steps of the context are ordered
+ * before it, see fd_batch_step).  Not part of the method: a probe to run every so many
+ * steps. */
 int fd_check_finite(fd_ctx *ctx, int *finite);
 
 /* Copy the state (u^n, u^{n-1}) out of / into the context.
@@ -269,12 +269,18 @@ int fd_batch_create(fd_batch **out, int max_shots, void *workspace, size_t ws_by
 int fd_batch_destroy(fd_batch *b);
 
 /* Replace the member set.  Each context advances until its step reaches target[i] (host
- * array); members keep their state and step.  Invalidates the captured graph. */
+ * array); members keep their state and step.  Invalidates the captured graph.  Work still
+ * queued on a member's own stream is completed before any batched launch touches it (the
+ * batch stream waits for each member stream); the call also waits on the host for earlier
+ * batched work, whose shot table it rewrites. */
 int fd_batch_set(fd_batch *b, fd_ctx *const *ctxs, const int64_t *target, int nctx);
 
-/* Enqueue nsteps batched steps (nsteps even uses a captured graph chunk of that length;
- * odd lengths fall back to direct launches).  Members already at their target do no work.
- * Host step mirrors advance immediately; call fd_sync on a member (or the stream) to wait. */
+/* Enqueue nsteps batched steps on the batch stream (nsteps even uses a captured graph
+ * chunk of that length; odd lengths fall back to direct launches).  Members already at
+ * their target do no work.  Host step mirrors advance immediately.  Each member's own
+ * stream is made to wait for these steps, so later calls on a member (fd_sync,
+ * fd_get_state, fd_check_finite, fd_step) are ordered after them; fd_sync on a member
+ * waits for them. */
 int fd_batch_step(fd_batch *b, int64_t nsteps);
 
 /* ----------------------------------------------------------------- measurement helpers */

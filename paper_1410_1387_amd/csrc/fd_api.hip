@@ -903,6 +903,7 @@ struct fd_batch {
     char *ws;
     hipStream_t stream;
     hipStream_t cap_stream;
+    hipEvent_t order_ev;  // orders member streams and the batch stream (no timing)
     std::vector<fd_ctx *> members;
     std::vector<int64_t> target;
     std::vector<ShotDesc> h_desc;
@@ -943,6 +944,12 @@ extern "C" int fd_batch_create(fd_batch **out, int max_shots, void *workspace, s
         delete b;
         return fail(FD_E_DEVICE, "fd_batch_create: %s", hipGetErrorString(e));
     }
+    e = hipEventCreateWithFlags(&b->order_ev, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        (void)hipStreamDestroy(b->cap_stream);
+        delete b;
+        return fail(FD_E_DEVICE, "fd_batch_create: %s", hipGetErrorString(e));
+    }
     *out = b;
     return FD_OK;
 }
@@ -960,35 +967,34 @@ extern "C" int fd_batch_destroy(fd_batch *b)
     if (!b) return fail(FD_E_INVAL, "fd_batch_destroy: null batch");
     (void)hipStreamSynchronize(b->stream);
     batch_drop_graph(b);
+    (void)hipEventDestroy(b->order_ev);
     (void)hipStreamDestroy(b->cap_stream);
     delete b;
     return FD_OK;
 }
 
-extern "C" int fd_batch_set(fd_batch *b, fd_ctx *const *ctxs, const int64_t *target, int nctx)
+// Validate a member set and build its shot table: descriptors with both step-counter
+// slots at the member's step, the member's target and the batch's z chunking, plus the
+// workgroup prefix.
+static int batch_table(fd_ctx *const *ctxs, const int64_t *target, int nctx, const char *who,
+                       std::vector<ShotDesc> &desc, std::vector<int32_t> &prefix, const FwdEntry **kf_out)
 {
-    if (!b || nctx < 0 || nctx > b->max_shots || (nctx > 0 && (!ctxs || !target)))
-        return fail(FD_E_INVAL, "fd_batch_set: bad arguments");
     const FwdEntry *kf = nullptr;
     for (int i = 0; i < nctx; ++i) {
         fd_ctx *c = ctxs[i];
         int st = check_ctx(c);
         if (st) return st;
-        if (c->bc != FD_BC_ZERO) return fail(FD_E_INVAL, "fd_batch_set: member %d is not zero-boundary", i);
+        if (c->bc != FD_BC_ZERO) return fail(FD_E_INVAL, "%s: member %d is not zero-boundary", who, i);
         if (!kf) kf = c->kf;
-        if (c->kf != kf) return fail(FD_E_INVAL, "fd_batch_set: member %d uses another kernel (r/dtype/ndim/tile)", i);
-        if (target[i] < c->step) return fail(FD_E_INVAL, "fd_batch_set: target below the member's step");
+        if (c->kf != kf) return fail(FD_E_INVAL, "%s: member %d uses another kernel (r/dtype/ndim/tile)", who, i);
+        if (target[i] < c->step) return fail(FD_E_INVAL, "%s: target below the member's step", who);
         if (c->nrec > 0 && target[i] - c->rec_base > c->rec_cap)
-            return fail(FD_E_RANGE, "fd_batch_set: member %d target exceeds its trace capacity", i);
+            return fail(FD_E_RANGE, "%s: member %d target exceeds its trace capacity", who, i);
+        for (int j = 0; j < i; ++j)
+            if (ctxs[j] == c) return fail(FD_E_INVAL, "%s: member %d appears twice", who, i);
     }
-    // wait for earlier batched work before rewriting the shot table it reads
-    hipError_t e = hipStreamSynchronize(b->stream);
-    if (e != hipSuccess) return fail(FD_E_DEVICE, "fd_batch_set: %s", hipGetErrorString(e));
-    batch_drop_graph(b);
-    b->members.assign(ctxs, ctxs + nctx);
-    b->target.assign(target, target + nctx);
-    b->h_desc.resize((size_t)nctx);
-    b->h_prefix.assign((size_t)nctx + 1, 0);
+    desc.resize((size_t)nctx);
+    prefix.assign((size_t)nctx + 1, 0);
     // Re-chunk the members for the batch as a whole: the other shots supply parallelism,
     // so each shot can march longer z chunks (fewer prologue re-reads) than it would
     // alone.  For a target length Z every member takes c = ceil(nz / Z) chunks of equal
@@ -1033,9 +1039,42 @@ extern "C" int fd_batch_set(fd_batch *b, fd_ctx *const *ctxs, const int64_t *tar
         d.target = target[i];
         d.zch = (int32_t)zchm[(size_t)i];
         d.chunks_z = (int32_t)((c->L.knz + d.zch - 1) / d.zch);
-        b->h_desc[(size_t)i] = d;
-        b->h_prefix[(size_t)i + 1] = b->h_prefix[(size_t)i] + (int32_t)(c->tiles_x * c->tiles_y * d.chunks_z);
+        desc[(size_t)i] = d;
+        const int64_t next = (int64_t)prefix[(size_t)i] + c->tiles_x * c->tiles_y * d.chunks_z;
+        if (next > INT32_MAX) return fail(FD_E_RANGE, "%s: too many workgroups in one launch", who);
+        prefix[(size_t)i + 1] = (int32_t)next;
     }
+    *kf_out = kf;
+    return FD_OK;
+}
+
+extern "C" int fd_batch_set(fd_batch *b, fd_ctx *const *ctxs, const int64_t *target, int nctx)
+{
+    if (!b || nctx < 0 || nctx > b->max_shots || (nctx > 0 && (!ctxs || !target)))
+        return fail(FD_E_INVAL, "fd_batch_set: bad arguments");
+    std::vector<ShotDesc> desc;
+    std::vector<int32_t> prefix;
+    const FwdEntry *kf = nullptr;
+    int st = batch_table(ctxs, target, nctx, "fd_batch_set", desc, prefix, &kf);
+    if (st) return st;
+    // Work a member still has queued on its own stream (steps, state uploads, source or
+    // receiver tables) must finish before a batched launch touches that member: the batch
+    // stream waits for each member stream's current tail (one event, re-recorded per
+    // stream; a wait binds to the record made before it).
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < nctx && e == hipSuccess; ++i) {
+        if (ctxs[i]->stream == b->stream) continue;
+        e = hipEventRecord(b->order_ev, ctxs[i]->stream);
+        if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, b->order_ev, 0);
+    }
+    // wait for earlier batched work before rewriting the shot table it reads
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return fail(FD_E_DEVICE, "fd_batch_set: %s", hipGetErrorString(e));
+    batch_drop_graph(b);
+    b->members.assign(ctxs, ctxs + nctx);
+    b->target.assign(target, target + nctx);
+    b->h_desc.swap(desc);
+    b->h_prefix.swap(prefix);
     b->nwg = b->h_prefix[(size_t)nctx];
     b->kf = kf;
     b->slot = 0;
@@ -1105,6 +1144,16 @@ extern "C" int fd_batch_step(fd_batch *b, int64_t nsteps)
         if (e != hipSuccess) return fail(FD_E_DEVICE, "fd_batch_step: %s", hipGetErrorString(e));
         b->slot ^= 1;
         ++done;
+    }
+    // Later work on a member's own stream (fd_sync, fd_get_state, fd_step, ...) is ordered
+    // after these batched steps: each member stream waits for the batch stream's tail.
+    bool other = false;
+    for (const fd_ctx *c : b->members) other = other || c->stream != b->stream;
+    if (other) {
+        hipError_t e = hipEventRecord(b->order_ev, b->stream);
+        for (size_t i = 0; i < b->members.size() && e == hipSuccess; ++i)
+            if (b->members[i]->stream != b->stream) e = hipStreamWaitEvent(b->members[i]->stream, b->order_ev, 0);
+        if (e != hipSuccess) return fail(FD_E_DEVICE, "fd_batch_step: %s", hipGetErrorString(e));
     }
     for (size_t i = 0; i < b->members.size(); ++i) {
         fd_ctx *c = b->members[i];

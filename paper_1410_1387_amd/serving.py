@@ -4,7 +4,8 @@
 
 * requests are submitted at any time (``submit`` returns a Future);
 * the loop admits queued requests in arrival order while their HBM footprint
-  (workspace + traces + wavelet) fits the budget and a batch slot is free; a shot's
+  (workspace + traces + wavelet, plus the dense velocity model that is on the device
+  only while the shot is set up) fits the budget and a batch slot is free; a shot's
   context is created on a separate setup stream, so admission overlaps with the
   batched work already on the GPU;
 * the admitted shots -- different grid sizes, same radius and dtype -- that make up
@@ -107,6 +108,13 @@ def shot_footprint(shape, nsteps: int, nrec: int, r: int, dtype: str) -> int:
     return F.fd_workspace_bytes(shape, r, dtype, 1, nrec) + (nsteps * nrec + nsteps) * es
 
 
+def staging_bytes(shape, dtype: str) -> int:
+    """HBM bytes a shot holds only while it is being set up: the dense velocity model on the
+    device (read by fd_create into c, then freed).  A velocity callable that returns a device
+    tensor in another dtype briefly holds its own copy as well."""
+    return int(np.prod(shape)) * (4 if dtype == "f32" else 8)
+
+
 class _ShotFactory:
     """Creates one shot's context and device buffers on a given stream."""
 
@@ -171,7 +179,7 @@ class ShotServer:
         self.t0 = time.perf_counter()
         self.stats = {"chunks": 0, "membership_changes": 0, "max_resident_bytes": 0, "max_resident_shots": 0,
                       "max_stepping_shots": 0, "gpu_points": 0, "gpu_busy_s": 0.0, "chunk_points": 0,
-                      "admit_s": 0.0}
+                      "admit_s": 0.0, "max_admission_bytes": 0}
         self._error: Optional[BaseException] = None
 
     # ------------------------------------------------------------------ public API
@@ -283,16 +291,19 @@ class ShotServer:
                         self._outstanding.discard(fut)
                         continue
                     try:
-                        need = shot_footprint(req.grid_shape(), req.nsteps, len(req.receivers), self.r, self.dtype)
+                        shape = req.grid_shape()
+                        need = shot_footprint(shape, req.nsteps, len(req.receivers), self.r, self.dtype)
+                        peak = need + staging_bytes(shape, self.dtype)  # while the model is staged
                     except Exception as e:  # malformed request
                         pending.popleft()
                         self._fail(req, arrival, fut, f"bad request: {e}")
                         continue
-                    if need > self.budget:
+                    if peak > self.budget:
                         pending.popleft()
-                        self._fail(req, arrival, fut, f"footprint {need} B exceeds the budget {self.budget} B")
+                        self._fail(req, arrival, fut, f"footprint {need} B + {peak - need} B of staged model "
+                                                      f"exceeds the budget {self.budget} B")
                         continue
-                    if used + need > self.budget:
+                    if used + peak > self.budget:
                         break  # wait for memory: head-of-line order is kept
                     pending.popleft()
                     if not fut.set_running_or_notify_cancel():  # cancelled just now
@@ -308,6 +319,7 @@ class ShotServer:
                     for t in tensors + [traces]:  # written by batched kernels on bstream
                         t.record_stream(bstream)
                     self.stats["admit_s"] += time.perf_counter() - t_adm
+                    self.stats["max_admission_bytes"] = max(self.stats["max_admission_bytes"], used + peak)
                     active.append(_Live(req, ctx, tensors, traces, fp, npts, arrival, self.now(), fut))
                     used += fp
                     dirty = True

@@ -88,6 +88,54 @@ def test_batched_graph_replays_match_single(oracle_mod):
     assert rel_l2(refs[1][1], ref["traces"]) <= 1e-4
 
 
+def test_batch_orders_member_streams(oracle_mod):
+    # Each member on a stream of its own and the batch on another: single steps still
+    # queued on a member's stream finish before the batch steps it, and a state read
+    # enqueued on the member's stream after fd_batch_step sees the batched steps; the
+    # batch stream itself is never synchronised by the test.
+    import torch
+
+    from paper_1410_1387_amd import fdwave as F
+
+    shots = [_shot((40, 48, 64), 60, 11), _shot((64, 64, 64), 50, 12), _shot((24, 90, 33), 44, 13)]
+    dt = 0.45 * min(oracle_mod.dt_max(3, 4, 10.0, float(s[0].max())) for s in shots)
+    pre = 7                                      # single steps queued before the batch
+    ref = []
+    s0 = torch.cuda.Stream()
+    for (v, src, rec, T) in shots:
+        ctx, keep, tr = _make_ctx(v, src, rec, T, dt, s0)
+        F.fd_step(ctx, T)
+        u = torch.empty(v.shape, dtype=torch.float32, device="cuda")
+        F.fd_get_state(ctx, u, None)
+        F.fd_sync(ctx)
+        ref.append((u.cpu().numpy(), tr.cpu().numpy()))
+        F.fd_destroy(ctx)
+    streams = [torch.cuda.Stream() for _ in shots]
+    bstream = torch.cuda.Stream()
+    ctxs = [_make_ctx(v, src, rec, T, dt, st) for (v, src, rec, T), st in zip(shots, streams)]
+    for ctx, keep, tr in ctxs:
+        F.fd_step(ctx, pre)                     # asynchronous, not waited for
+    bws = torch.empty(F.fd_batch_workspace_bytes(4), dtype=torch.uint8, device="cuda")
+    b = F.fd_batch_create(4, bws, F.stream_ptr(bstream))
+    F.fd_batch_set(b, [c[0] for c in ctxs], [s[3] for s in shots])
+    say("batch on its own stream, members on theirs")
+    for _ in range(4):
+        F.fd_batch_step(b, 16)
+    outs = []
+    for (ctx, keep, tr), (v, *_rest) in zip(ctxs, shots):
+        u = torch.empty(v.shape, dtype=torch.float32, device="cuda")
+        F.fd_get_state(ctx, u, None)            # on the member's stream
+        F.fd_sync(ctx)
+        outs.append((u.cpu().numpy(), tr.cpu().numpy(), F.fd_get_step(ctx)))
+    for j, ((u, tr, n), (u_ref, tr_ref)) in enumerate(zip(outs, ref)):
+        assert n == shots[j][3]
+        assert np.array_equal(u, u_ref), j
+        assert np.array_equal(tr, tr_ref), j
+    F.fd_batch_destroy(b)
+    for ctx, keep, tr in ctxs:
+        F.fd_destroy(ctx)
+
+
 def _requests(n, seed, sides=(24, 32, 40), steps=(40, 90), spread=0.3):
     from paper_1410_1387_amd.serving import ShotRequest
 
@@ -124,17 +172,34 @@ def test_server_alone_vs_mix_bitwise(oracle_mod):
 
 
 def test_server_budget_backpressure():
-    from paper_1410_1387_amd.serving import ShotServer, run_sequential, shot_footprint
+    import torch
+
+    from paper_1410_1387_amd import fdwave as F
+    from paper_1410_1387_amd.serving import ShotServer, run_sequential, shot_footprint, staging_bytes
 
     reqs = _requests(6, 6, sides=(32, 40), spread=0.0)
-    need = max(shot_footprint(q.velocity.shape, q.nsteps, len(q.receivers), 4, "f32") for q in reqs)
+    need = max(shot_footprint(q.velocity.shape, q.nsteps, len(q.receivers), 4, "f32") +
+               staging_bytes(q.velocity.shape, "f32") for q in reqs)
     budget = int(need * 1.6)  # room for one shot at a time, sometimes two
     say(f"budget {budget} B")
     srv = ShotServer(r=4, chunk=8, max_shots=8, budget_bytes=budget)
+    torch.cuda.synchronize()
+    base = torch.cuda.memory_allocated()
+    torch.cuda.reset_peak_memory_stats()
     res = {r.rid: r for r in srv.serve_trace(reqs, realtime=False)}
+    torch.cuda.synchronize()
+    peak = torch.cuda.max_memory_allocated() - base
     seq = {r.rid: r for r in run_sequential(reqs, realtime=False)}
     assert all(r.status == "ok" for r in res.values())
     assert srv.stats["max_resident_bytes"] <= budget
+    assert srv.stats["max_admission_bytes"] <= budget
+    # the device memory the server really allocated, staged models included, stays within the
+    # budget plus its own batch table, the traces it has already handed back (they belong to
+    # the caller once a shot completes) and the allocator's 512-byte rounding of each tensor
+    handed_back = sum(r.traces.numel() * r.traces.element_size() for r in res.values())
+    slack = F.fd_batch_workspace_bytes(8) + 64 * 1024
+    say(f"peak device allocation {peak} B against budget {budget} B (+ {handed_back} B of returned traces)")
+    assert peak <= budget + handed_back + slack
     for rid in res:
         assert np.array_equal(res[rid].traces.cpu().numpy(), seq[rid].traces.cpu().numpy())
 
