@@ -30,6 +30,7 @@ static const FwdEntry k3_r4[] = {
     fwd_entry<TileCfg<float, 4, 3, 16, 32, 2>>("f32 r4 3d tile 64x64 (512 thr, 2 row/thr)"),
     fwd_entry<TileCfg<float, 4, 3, 32, 16, 2>>("f32 r4 3d tile 128x32 (512 thr, 2 row/thr)"),
     fwd_entry<TileCfg<float, 4, 3, 8, 32, 2>>("f32 r4 3d tile 32x64 (256 thr, 2 row/thr)"),
+    fwd_entry<TileCfg<float, 4, 3, 8, 32, 1>>("f32 r4 3d tile 32x32 (256 thr, 1 row/thr)"),
 };
 static const FwdEntry k2_r4[] = {
     fwd_entry<TileCfg<float, 4, 2, 64, 1, 1>>("f32 r4 2d tile 256x1 (64 thr, 1 row/thr)"),
@@ -57,6 +58,11 @@ static const FwdEntry k3_r8[] = {
     fwd_entry<TileCfg<float, 8, 3, 16, 16, 1>>("f32 r8 3d tile 64x16 (256 thr, 1 row/thr)"),
     fwd_entry<TileCfg<float, 8, 3, 32, 8, 1>>("f32 r8 3d tile 128x8 (256 thr, 1 row/thr)"),
     fwd_entry<TileCfg<float, 8, 3, 16, 32, 1>>("f32 r8 3d tile 64x32 (512 thr, 1 row/thr)"),
+    fwd_entry<TileCfg<float, 8, 3, 32, 16, 1, 2>>("f32 r8 3d tile 64x16 (512 thr, 1 row/thr, 8-byte vectors)"),
+    fwd_entry<TileCfg<float, 8, 3, 32, 8, 1, 2>>("f32 r8 3d tile 64x8 (256 thr, 1 row/thr, 8-byte vectors)"),
+    fwd_entry<TileCfg<float, 8, 3, 64, 8, 1, 2>>("f32 r8 3d tile 128x8 (512 thr, 1 row/thr, 8-byte vectors)"),
+    fwd_entry<TileCfg<float, 8, 3, 16, 16, 1, 2>>("f32 r8 3d tile 32x16 (256 thr, 1 row/thr, 8-byte vectors)"),
+    fwd_entry<TileCfg<float, 8, 3, 64, 4, 1, 2>>("f32 r8 3d tile 128x4 (256 thr, 1 row/thr, 8-byte vectors)"),
 };
 static const FwdEntry k2_r8[] = {
     fwd_entry<TileCfg<float, 8, 2, 64, 1, 1>>("f32 r8 2d tile 256x1 (64 thr, 1 row/thr)"),

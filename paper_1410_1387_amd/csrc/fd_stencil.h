@@ -90,53 +90,51 @@ struct StencilWeights {
     }
 };
 
-// ------------------------------------------------------------------ 16-byte vectors
+// ------------------------------------------------------------------ x vectors
 
-template <typename T>
-struct V16;
-template <>
-struct V16<float> {
-    typedef float t __attribute__((ext_vector_type(4)));
-    static constexpr int N = 4;
+// N consecutive x points of one row, moved with one load or store instruction.  The
+// kernels use 16-byte vectors (4 floats, 2 doubles) unless a tile asks for 8-byte ones.
+template <typename T, int N>
+struct VecT {
+    typedef T t __attribute__((ext_vector_type(N)));
 };
-template <>
-struct V16<double> {
-    typedef double t __attribute__((ext_vector_type(2)));
-    static constexpr int N = 2;
+template <typename T>
+struct V16 {
+    static constexpr int N = 16 / (int)sizeof(T);
 };
 
-template <typename T>
-__device__ __forceinline__ void vld(T (&d)[V16<T>::N], const T *p)
+template <typename T, int N>
+__device__ __forceinline__ void vld(T (&d)[N], const T *p)
 {
-    typename V16<T>::t v = *reinterpret_cast<const typename V16<T>::t *>(p);
+    typename VecT<T, N>::t v = *reinterpret_cast<const typename VecT<T, N>::t *>(p);
 #pragma unroll
-    for (int i = 0; i < V16<T>::N; ++i) d[i] = v[i];
+    for (int i = 0; i < N; ++i) d[i] = v[i];
 }
 
-template <typename T>
-__device__ __forceinline__ void vld_nt(T (&d)[V16<T>::N], const T *p)
+template <typename T, int N>
+__device__ __forceinline__ void vld_nt(T (&d)[N], const T *p)
 {
-    typename V16<T>::t v = __builtin_nontemporal_load(reinterpret_cast<const typename V16<T>::t *>(p));
+    typename VecT<T, N>::t v = __builtin_nontemporal_load(reinterpret_cast<const typename VecT<T, N>::t *>(p));
 #pragma unroll
-    for (int i = 0; i < V16<T>::N; ++i) d[i] = v[i];
+    for (int i = 0; i < N; ++i) d[i] = v[i];
 }
 
-template <typename T>
-__device__ __forceinline__ void vst(T *p, const T (&s)[V16<T>::N])
+template <typename T, int N>
+__device__ __forceinline__ void vst(T *p, const T (&s)[N])
 {
-    typename V16<T>::t v;
+    typename VecT<T, N>::t v;
 #pragma unroll
-    for (int i = 0; i < V16<T>::N; ++i) v[i] = s[i];
-    *reinterpret_cast<typename V16<T>::t *>(p) = v;
+    for (int i = 0; i < N; ++i) v[i] = s[i];
+    *reinterpret_cast<typename VecT<T, N>::t *>(p) = v;
 }
 
-template <typename T>
-__device__ __forceinline__ void vst_nt(T *p, const T (&s)[V16<T>::N])
+template <typename T, int N>
+__device__ __forceinline__ void vst_nt(T *p, const T (&s)[N])
 {
-    typename V16<T>::t v;
+    typename VecT<T, N>::t v;
 #pragma unroll
-    for (int i = 0; i < V16<T>::N; ++i) v[i] = s[i];
-    __builtin_nontemporal_store(v, reinterpret_cast<typename V16<T>::t *>(p));
+    for (int i = 0; i < N; ++i) v[i] = s[i];
+    __builtin_nontemporal_store(v, reinterpret_cast<typename VecT<T, N>::t *>(p));
 }
 
 template <typename T, int N>
@@ -186,7 +184,7 @@ __device__ __forceinline__ int lower_bound_z(const Event *ev, int lo, int hi, in
 
 // ------------------------------------------------------------------ tile configuration
 
-template <typename T, int R_, int NDIM_, int TXN_, int TYN_, int EY_>
+template <typename T, int R_, int NDIM_, int TXN_, int TYN_, int EY_, int VEC_ = V16<T>::N>
 struct TileCfg {
     typedef T type;
     static constexpr int R = R_;
@@ -194,7 +192,7 @@ struct TileCfg {
     static constexpr int TXN = TXN_;                       // threads along x
     static constexpr int TYN = (NDIM_ == 3) ? TYN_ : 1;    // threads along y
     static constexpr int EY = (NDIM_ == 3) ? EY_ : 1;      // rows per thread
-    static constexpr int VEC = V16<T>::N;                  // x points per thread
+    static constexpr int VEC = VEC_;                       // x points per thread (one vector)
     static constexpr int NT = TXN * TYN;
     static constexpr int BX = TXN * VEC;
     static constexpr int BY = TYN * EY;
@@ -938,5 +936,7 @@ const FwdEntry *fwd_configs_f32(int r, int ndim, int *count);
 const FwdEntry *fwd_configs_f64(int r, int ndim, int *count);
 const AdjEntry *adj_config_f32(int r, int ndim);
 const AdjEntry *adj_config_f64(int r, int ndim);
+const AdjEntry *adj_configs_f32(int r, int ndim, int *count);
+const AdjEntry *adj_configs_f64(int r, int ndim, int *count);
 
 }  // namespace fdw

@@ -16,10 +16,11 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 # 64x16 with one row per thread first: 138 VGPRs and 41 KB of LDS give three 256-thread
 # workgroups per CU, and at 512^3 r = 4 the chunker fills them with 768 workgroups of
 # 171 planes (352 Gpts/s against 342 for 64x32 with two rows per thread)
-F32_3D = [(16, 16, 1), (16, 16, 2), (32, 8, 2), (16, 8, 4), (16, 32, 2), (32, 16, 2), (8, 32, 2)]
+F32_3D = [(16, 16, 1), (16, 16, 2), (32, 8, 2), (16, 8, 4), (16, 32, 2), (32, 16, 2), (8, 32, 2), (8, 32, 1)]
 # radii above 4 keep one row per thread: two rows exceed 256 VGPRs and spill; 128x16
 # (512 threads) first: measured fastest at 384^3, r = 8
-F32_3D_BIG_R = [(32, 16, 1), (16, 16, 1), (32, 8, 1), (16, 32, 1)]
+F32_3D_BIG_R = [(32, 16, 1), (16, 16, 1), (32, 8, 1), (16, 32, 1),
+                (32, 16, 1, 2), (32, 8, 1, 2), (64, 8, 1, 2), (16, 16, 1, 2), (64, 4, 1, 2)]
 # FP64: 32x32 (two rows per thread) first for radii <= 4: 64x16 with 512 threads needs
 # 83 KB of LDS at r = 4, one workgroup per CU (512^3 r = 4: 174.6 vs 129.2 Gpts/s);
 # larger radii keep one row per thread (two rows spill at r >= 7); 32x16 measured fastest
@@ -29,10 +30,12 @@ F64_3D_BIG_R = [(16, 16, 1), (32, 16, 1), (32, 8, 1)]
 F32_SWEEP_RADII = {4, 8}
 F64_SWEEP_RADII = {4, 8}
 F2D = (64, 1, 1)          # 2-D forward and adjoint: one row of 64 threads
-ADJ_F32_3D = (32, 16, 1)        # radii <= 4 (measured 5-7 % faster than 64x16)
-ADJ_F32_3D_BIG_R = (16, 16, 1)  # radii > 4: two queues of 2r+2 planes need the smaller tile
-ADJ_F64_3D = (32, 16, 1)        # radii <= 4: 64x16, 512 threads (256^3: 176.0 vs 189.8 us for 64x8)
-ADJ_F64_3D_BIG_R = (32, 8, 1)
+# adjoint: radii <= 4 128x16 first (measured 5-7 % faster than 64x16)
+ADJ_F32_3D = [(32, 16, 1), (32, 16, 1, 2), (64, 8, 1, 2), (32, 8, 1, 2), (16, 16, 1, 2)]
+ADJ_F32_3D_BIG_R = [(16, 16, 1), (32, 16, 1, 2)]  # radii > 4: two queues of 2r+2 planes
+ADJ_F64_3D = [(32, 16, 1)]        # radii <= 4: 64x16, 512 threads (256^3: 176.0 vs 189.8 us for 64x8)
+ADJ_F64_3D_BIG_R = [(32, 8, 1)]
+ADJ_SWEEP_RADII = {4, 8}
 # VTI kernel: (xy radius, z radius) pairs and tile shapes (threads along x, rows along y)
 VTI_RADII = [(2, 1), (2, 2), (4, 1), (4, 2), (4, 4), (8, 1), (8, 2), (8, 4), (8, 8),
              (12, 1), (12, 2), (12, 4), (12, 8)]
@@ -49,12 +52,20 @@ namespace fdw {{
 """
 
 
-def cfgname(T, R, nd, txn, tyn, ey):
-    vec = 4 if T == "float" else 2
+def cfgname(T, R, nd, txn, tyn, ey, vec=None):
+    full = 4 if T == "float" else 2
+    vec = vec or full
     bx = txn * vec
     by = tyn * ey if nd == 3 else 1
     nt = txn * (tyn if nd == 3 else 1)
-    return f"{'f32' if T == 'float' else 'f64'} r{R} {nd}d tile {bx}x{by} ({nt} thr, {ey if nd == 3 else 1} row/thr)"
+    name = f"{'f32' if T == 'float' else 'f64'} r{R} {nd}d tile {bx}x{by} ({nt} thr, {ey if nd == 3 else 1} row/thr"
+    return name + (f", {vec * (4 if T == 'float' else 8)}-byte vectors)" if vec != full else ")")
+
+
+def tilecfg(T, R, nd, txn, tyn, ey, vec=None):
+    """TileCfg<...> for a tile tuple (threads along x, threads along y, rows per thread
+    [, x points per thread when narrower than one 16-byte vector])."""
+    return f"TileCfg<{T}, {R}, {nd}, {txn}, {tyn}, {ey}" + (f", {vec}>" if vec else ">")
 
 
 def fwd_file(T, sweep3d, sweep_radii, sweep3d_big_r=None):
@@ -64,8 +75,8 @@ def fwd_file(T, sweep3d, sweep_radii, sweep3d_big_r=None):
         lst = sweep3d_big_r if (sweep3d_big_r and R > 4) else sweep3d
         cfgs3 = lst if R in sweep_radii else lst[:1]
         out += f"static const FwdEntry k3_r{R}[] = {{\n"
-        for (txn, tyn, ey) in cfgs3:
-            out += f'    fwd_entry<TileCfg<{T}, {R}, 3, {txn}, {tyn}, {ey}>>("{cfgname(T, R, 3, txn, tyn, ey)}"),\n'
+        for cfg in cfgs3:
+            out += f'    fwd_entry<{tilecfg(T, R, 3, *cfg)}>("{cfgname(T, R, 3, *cfg)}"),\n'
         out += "};\n"
         txn = F2D[0]
         out += f"static const FwdEntry k2_r{R}[] = {{\n"
@@ -81,20 +92,28 @@ def fwd_file(T, sweep3d, sweep_radii, sweep3d_big_r=None):
 
 
 def adj_file(T, d3, d3_big_r=None):
+    """Adjoint kernels: a list of 3-D tile shapes per radius (the first is the default)
+    and one 2-D shape."""
     tag = "f32" if T == "float" else "f64"
     out = HDR.format(fname=f"fd_adj_{tag}.hip", what="adjoint", T=T)
     for R in range(1, 9):
-        txn, tyn, ey = d3_big_r if (d3_big_r and R > 4) else d3
-        out += (f"static const AdjEntry a3_r{R} = adj_entry<TileCfg<{T}, {R}, 3, {txn}, {tyn}, {ey}>>"
-                f'("{cfgname(T, R, 3, txn, tyn, ey)}");\n')
+        lst = d3_big_r if (d3_big_r and R > 4) else d3
+        lst = lst if R in ADJ_SWEEP_RADII else lst[:1]
+        out += f"static const AdjEntry a3_r{R}[] = {{\n"
+        for cfg in lst:
+            out += f'    adj_entry<{tilecfg(T, R, 3, *cfg)}>("{cfgname(T, R, 3, *cfg)}"),\n'
+        out += "};\n"
         txn = F2D[0]
-        out += (f"static const AdjEntry a2_r{R} = adj_entry<TileCfg<{T}, {R}, 2, {txn}, 1, 1>>"
-                f'("{cfgname(T, R, 2, txn, 1, 1)}");\n')
-    out += "\nconst AdjEntry *adj_config_" + tag + "(int r, int ndim)\n{\n    switch (r * 10 + ndim) {\n"
+        out += (f"static const AdjEntry a2_r{R}[] = {{adj_entry<TileCfg<{T}, {R}, 2, {txn}, 1, 1>>"
+                f'("{cfgname(T, R, 2, txn, 1, 1)}")}};\n')
+    out += "\nconst AdjEntry *adj_configs_" + tag + "(int r, int ndim, int *count)\n{\n    switch (r * 10 + ndim) {\n"
     for R in range(1, 9):
         for nd in (2, 3):
-            out += f"    case {R * 10 + nd}: return &a{nd}_r{R};\n"
-    out += "    default: return nullptr;\n    }\n}\n\n}  // namespace fdw\n"
+            out += (f"    case {R * 10 + nd}: *count = (int)(sizeof(a{nd}_r{R}) / sizeof(AdjEntry)); "
+                    f"return a{nd}_r{R};\n")
+    out += "    default: *count = 0; return nullptr;\n    }\n}\n\n"
+    out += ("const AdjEntry *adj_config_" + tag + "(int r, int ndim)\n{\n    int n = 0;\n"
+            "    return adj_configs_" + tag + "(r, ndim, &n);\n}\n\n}  // namespace fdw\n")
     with open(os.path.join(HERE, f"fd_adj_{tag}.hip"), "w") as f:
         f.write(out)
 
