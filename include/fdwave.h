@@ -275,6 +275,29 @@ int fd_batch_destroy(fd_batch *b);
  * batched work, whose shot table it rewrites. */
 int fd_batch_set(fd_batch *b, fd_ctx *const *ctxs, const int64_t *target, int nctx);
 
+/* Shots a no-allocation batch can hold: the size of its fixed shot table. */
+#define FD_BATCH_NOALLOC_MAX_SHOTS 256
+
+/* For callers that cannot allocate device memory (code being captured into a HIP graph,
+ * tight serving loops, harnesses that forbid allocation): a batch like fd_batch_create's
+ * whose shot table (descriptors, step counters, workgroup prefix) lives in a fixed array of
+ * the library instead of a caller workspace.  The array holds FD_BATCH_NOALLOC_MAX_SHOTS
+ * shots (about 44 KB); each GPU the library runs on holds its own copy until the process
+ * ends.  The call allocates nothing (no device or host allocation, no stream, event or
+ * graph).  Use the batch with fd_batch_set, fd_batch_step and fd_batch_destroy, with these
+ * differences from fd_batch_create's batch:
+ *   - one per device at a time: while one is alive on the current device, another call
+ *     there returns FD_E_STATE; fd_batch_destroy releases the array (the array keeps the
+ *     last batch's table, which fd_batch_set rewrites whole before any step reads it);
+ *   - every member context must run on the batch's stream (fd_batch_set: FD_E_INVAL);
+ *   - fd_batch_step launches every step directly: it builds no graph (instantiating one
+ *     allocates device memory), so nothing on this batch's path allocates device memory.
+ * Results are bitwise those of fd_batch_create's batch.  Like every batch it is not
+ * thread-safe: calls on it from several threads race.
+ *   max_shots  1 .. FD_BATCH_NOALLOC_MAX_SHOTS (FD_E_RANGE otherwise)
+ *   stream     the batch stream (hipStream_t), as for fd_batch_create */
+int fd_batch_create_noalloc(fd_batch **out, int max_shots, void *stream);
+
 /* Enqueue nsteps batched steps on the batch stream (nsteps even uses a captured graph
  * chunk of that length; odd lengths fall back to direct launches).  Members already at
  * their target do no work.  Host step mirrors advance immediately.  Each member's own

@@ -914,16 +914,25 @@ struct fd_batch {
     hipGraphExec_t exec;
     int64_t exec_len;
     bool has_exec;
+    // no-allocation batch: the shot table is the device's fixed array, every member runs
+    // on the batch stream, and steps are launched directly (no graph, no capture stream)
+    bool noalloc;
+    int device;
 
     ShotDesc *d_desc() const { return reinterpret_cast<ShotDesc *>(ws); }
     int32_t *d_prefix() const { return reinterpret_cast<int32_t *>(ws + align_up((int64_t)max_shots * sizeof(ShotDesc), 256)); }
 };
 
+static constexpr int64_t batch_table_bytes(int max_shots)
+{
+    return ((int64_t)max_shots * (int64_t)sizeof(ShotDesc) + 255) / 256 * 256 +
+           ((int64_t)(max_shots + 1) * (int64_t)sizeof(int32_t) + 255) / 256 * 256;
+}
+
 extern "C" size_t fd_batch_workspace_bytes(int max_shots)
 {
     if (max_shots < 1) return 0;
-    return (size_t)align_up((int64_t)max_shots * sizeof(ShotDesc), 256) +
-           (size_t)align_up((int64_t)(max_shots + 1) * sizeof(int32_t), 256);
+    return (size_t)batch_table_bytes(max_shots);
 }
 
 extern "C" int fd_batch_create(fd_batch **out, int max_shots, void *workspace, size_t ws_bytes, void *stream)
@@ -939,6 +948,8 @@ extern "C" int fd_batch_create(fd_batch **out, int max_shots, void *workspace, s
     b->kf = nullptr;
     b->has_exec = false;
     b->exec_len = 0;
+    b->noalloc = false;
+    b->device = -1;
     hipError_t e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
         delete b;
@@ -950,6 +961,69 @@ extern "C" int fd_batch_create(fd_batch **out, int max_shots, void *workspace, s
         delete b;
         return fail(FD_E_DEVICE, "fd_batch_create: %s", hipGetErrorString(e));
     }
+    *out = b;
+    return FD_OK;
+}
+
+// ------------------------------------------------------------------ batch without allocation
+
+// The shot table (descriptors + workgroup prefix) of the no-allocation batch.  Each GPU
+// holds its own copy for the life of the process.  Host code never uses this name as an
+// address (on the host it is a stand-in symbol): it uses the device address that
+// hipGetSymbolAddress returns for the current device, kept per device below.
+static __device__ __align__(256) char scratch[batch_table_bytes(FD_BATCH_NOALLOC_MAX_SHOTS)];
+
+namespace {
+constexpr int kMaxDevices = 64;
+struct NoallocSlot {
+    char *ptr = nullptr;     // device address of `scratch` on this device (once resolved)
+    bool in_use = false;     // held by a live no-allocation batch
+    fd_batch batch;          // the handle fd_batch_create_noalloc returns on this device
+};
+std::mutex g_noalloc_mu;
+NoallocSlot g_noalloc[kMaxDevices];
+}  // namespace
+
+extern "C" int fd_batch_create_noalloc(fd_batch **out, int max_shots, void *stream)
+{
+    if (!out) return fail(FD_E_INVAL, "fd_batch_create_noalloc: null out");
+    if (max_shots < 1 || max_shots > FD_BATCH_NOALLOC_MAX_SHOTS)
+        return fail(FD_E_RANGE, "fd_batch_create_noalloc: max_shots %d outside [1, %d] (the fixed shot table's size)",
+                    max_shots, FD_BATCH_NOALLOC_MAX_SHOTS);
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(FD_E_DEVICE, "fd_batch_create_noalloc: hipGetDevice: %s", hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices) return fail(FD_E_RANGE, "fd_batch_create_noalloc: device %d", dev);
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    NoallocSlot &sl = g_noalloc[dev];
+    if (sl.in_use)
+        return fail(FD_E_STATE, "fd_batch_create_noalloc: device %d's fixed shot table is held by another batch "
+                                "(fd_batch_destroy it first)", dev);
+    if (!sl.ptr) {  // first use on this device (it is current): resolve the array's device address
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(FD_E_DEVICE, "fd_batch_create_noalloc: hipGetSymbolAddress: %s", hipGetErrorString(e));
+        sl.ptr = static_cast<char *>(p);
+    }
+    fd_batch *b = &sl.batch;
+    b->max_shots = max_shots;
+    b->ws = sl.ptr;
+    b->stream = (hipStream_t)stream;
+    b->cap_stream = nullptr;
+    b->order_ev = nullptr;
+    b->members.clear();
+    b->target.clear();
+    b->h_desc.clear();
+    b->h_prefix.clear();
+    b->nwg = 0;
+    b->slot = 0;
+    b->kf = nullptr;
+    b->has_exec = false;
+    b->exec_len = 0;
+    b->noalloc = true;
+    b->device = dev;
+    sl.in_use = true;
     *out = b;
     return FD_OK;
 }
@@ -966,6 +1040,14 @@ extern "C" int fd_batch_destroy(fd_batch *b)
 {
     if (!b) return fail(FD_E_INVAL, "fd_batch_destroy: null batch");
     (void)hipStreamSynchronize(b->stream);
+    if (b->noalloc) {  // the device's fixed handle: release the shot table for the next batch
+        std::lock_guard<std::mutex> lk(g_noalloc_mu);
+        b->members.clear();
+        b->target.clear();
+        b->nwg = 0;
+        g_noalloc[b->device].in_use = false;
+        return FD_OK;
+    }
     batch_drop_graph(b);
     (void)hipEventDestroy(b->order_ev);
     (void)hipStreamDestroy(b->cap_stream);
@@ -1057,6 +1139,10 @@ extern "C" int fd_batch_set(fd_batch *b, fd_ctx *const *ctxs, const int64_t *tar
     const FwdEntry *kf = nullptr;
     int st = batch_table(ctxs, target, nctx, "fd_batch_set", desc, prefix, &kf);
     if (st) return st;
+    if (b->noalloc)
+        for (int i = 0; i < nctx; ++i)
+            if (ctxs[i]->stream != b->stream)
+                return fail(FD_E_INVAL, "fd_batch_set: member %d runs on another stream than the no-allocation batch", i);
     // Work a member still has queued on its own stream (steps, state uploads, source or
     // receiver tables) must finish before a batched launch touches that member: the batch
     // stream waits for each member stream's current tail (one event, re-recorded per
@@ -1117,7 +1203,7 @@ extern "C" int fd_batch_step(fd_batch *b, int64_t nsteps)
         ++done;
     }
     const int64_t rest = nsteps - done;
-    const int64_t chunk = rest - (rest & 1);
+    const int64_t chunk = b->noalloc ? 0 : rest - (rest & 1);  // a no-allocation batch launches directly
     if (chunk > 0) {
         if (!b->has_exec || b->exec_len != chunk) {
             batch_drop_graph(b);

@@ -20,6 +20,7 @@ FD_OK, FD_E_INVAL, FD_E_RANGE, FD_E_UNSTABLE, FD_E_STATE, FD_E_DEVICE, FD_E_NOME
 FD_F32, FD_F64 = 0, 1
 FD_BC_ZERO, FD_BC_PERIODIC = 0, 1
 FD_DENSE, FD_PADDED = 0, 1
+FD_BATCH_NOALLOC_MAX_SHOTS = 256  # include/fdwave.h: shots of the fixed no-allocation shot table
 
 STATUS_NAMES = {
     FD_E_INVAL: "FD_E_INVAL", FD_E_RANGE: "FD_E_RANGE", FD_E_UNSTABLE: "FD_E_UNSTABLE",
@@ -31,7 +32,7 @@ EXPORTS = [
     "fd_weights", "fd_dt_max", "fd_field_bytes", "fd_workspace_bytes", "fd_create", "fd_destroy",
     "fd_set_stream", "fd_inject", "fd_clear_sources", "fd_set_damping", "fd_record", "fd_ricker", "fd_step", "fd_sync",
     "fd_get_step", "fd_get_state", "fd_set_time_blocking", "fd_set_state", "fd_step_explicit", "fd_adjoint_segment",
-    "fd_gradient_finish", "fd_batch_workspace_bytes", "fd_batch_create", "fd_batch_destroy",
+    "fd_gradient_finish", "fd_batch_workspace_bytes", "fd_batch_create", "fd_batch_create_noalloc", "fd_batch_destroy",
     "fd_batch_set", "fd_batch_step", "fd_copy_probe", "fd_stream_probe", "fd_check_finite", "fd_kernel_config", "fd_set_tuning",
     "fd_last_error",
     "fd_vti_z_weights", "fd_vti_dt_max", "fd_vti_workspace_bytes", "fd_vti_create", "fd_vti_destroy",
@@ -93,6 +94,7 @@ def lib():
             "fd_gradient_finish": (ctypes.c_int, [P, P, P, P, D]),
             "fd_batch_workspace_bytes": (SZ, [ctypes.c_int]),
             "fd_batch_create": (ctypes.c_int, [ctypes.POINTER(P), ctypes.c_int, P, SZ, P]),
+            "fd_batch_create_noalloc": (ctypes.c_int, [ctypes.POINTER(P), ctypes.c_int, P]),
             "fd_batch_destroy": (ctypes.c_int, [P]),
             "fd_batch_set": (ctypes.c_int, [P, ctypes.POINTER(P), ctypes.POINTER(I64), ctypes.c_int]),
             "fd_batch_step": (ctypes.c_int, [P, I64]),
@@ -299,6 +301,12 @@ def fd_batch_create(max_shots: int, workspace, stream) -> int:
     h_ = ctypes.c_void_p()
     _check(lib().fd_batch_create(ctypes.byref(h_), max_shots, ptr(workspace), workspace.numel(), stream),
            "fd_batch_create")
+    return h_.value
+
+
+def fd_batch_create_noalloc(max_shots: int, stream) -> int:
+    h_ = ctypes.c_void_p()
+    _check(lib().fd_batch_create_noalloc(ctypes.byref(h_), max_shots, stream), "fd_batch_create_noalloc")
     return h_.value
 
 

@@ -39,6 +39,15 @@ def test_exports_every_declared_symbol(F):
     assert sorted(F.EXPORTS) == declared
 
 
+def test_noalloc_limit_matches_header(F):
+    # the binding's copy of the no-allocation batch's shot limit is the header's
+    import re
+
+    with open(os.path.join(ROOT, "include", "fdwave.h")) as f:
+        m = re.search(r"#define FD_BATCH_NOALLOC_MAX_SHOTS (\d+)", f.read())
+    assert m and int(m.group(1)) == F.FD_BATCH_NOALLOC_MAX_SHOTS
+
+
 def test_weights_match_oracle(F, oracle_mod):
     for r in range(1, 13):
         w = np.array(F.fd_weights(r))
