@@ -10,13 +10,18 @@ A shot runs every row of the forward path on the GPU: model preparation
 stencil launches with the source and receivers fused in.  The velocity model is
 resident in HBM before the timed region starts.
 
-    python bench.py [--steps K] [--warmup W] [--no-cpu] [--no-vti] [--gradient] [--serving] [--copy-probe]
+    python bench.py [--steps K] [--warmup W] [--no-cpu] [--no-vti] [--no-gradient] [--no-serving]
+                    [--serving-pairs P] [--copy-probe]
     python bench.py --workload 3d_384_r8_noise_fp32      # the other forward workloads (also
     python bench.py --workload 3d_512_r4_layered_fp64    # 3d_512_r4_layered_fp32, the default)
     python bench.py --summarize-prof DIR [--workload W]  # rocprofv3 CSVs -> profiles/ summary
 
 The JSON line also carries the paper's own benchmark kernel, the two-field VTI
-propagator (R_xy = 12, R_z = 8) on a 512^3 FP32 grid, under "vti".
+propagator (R_xy = 12, R_z = 8) on a 512^3 FP32 grid, under "vti"; the 256^3 velocity
+gradient (forward with checkpoints, recompute, adjoint) under "gradient"; and the two
+serving traces under "serving", each served three times with continuous batching and
+three times one shot at a time, interleaved, with p50/p99 shot latency of the main
+trace (sides 128-400) on the top level.
 
 Prints one JSON line.
 """
@@ -342,7 +347,7 @@ def summarize_prof(d: str, workload: str = DEFAULT_WORKLOAD):
     probe_bytes = 1 << 30
     f_scale = probe_bytes / (mean(fetch[copy]) * 1024.0)
     w_scale = probe_bytes / (mean(write[copy]) * 1024.0)
-    bench_args = ("--steps 1 --warmup 0 --no-cpu --gradient --copy-probe" if workload == DEFAULT_WORKLOAD else
+    bench_args = ("--steps 1 --warmup 0 --no-cpu --no-serving --copy-probe" if workload == DEFAULT_WORKLOAD else
                   f"--workload {workload} --steps 1 --warmup 0 --no-cpu --no-vti --copy-probe")
     cmds = [
         f"rocprofv3 --kernel-trace --stats -d DIR/trace -o trace --output-format csv -- python3 bench.py {bench_args}",
@@ -383,9 +388,56 @@ def summarize_prof(d: str, workload: str = DEFAULT_WORKLOAD):
 # --------------------------------------------------------------------------- CPU baseline
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+# the oracle in a child process with its own OpenMP thread count (the oracle reads
+# OMP_NUM_THREADS when its library loads): a 1-step and a (1 + nsteps)-step call, whose
+# difference is the cost of nsteps steps without the per-call set-up; prints
+# {"pts_per_s": ..., "steps": nsteps, "s": seconds of those steps}
+_ORACLE_CHILD = """
+import json, sys, time
+import numpy as np
+sys.path.insert(0, {root!r})
+import bench, oracle
+shot = bench.forward_shot({workload!r})
+v = shot.velocity()
+dt = shot.courant * oracle.dt_max(3, shot.r, shot.h, v.max())
+u0 = np.random.default_rng(0).standard_normal(shot.shape)
+el = []
+for n in (1, 1 + {nsteps}):
+    t = time.perf_counter()
+    oracle.forward(v, shot.h, dt, shot.r, n, [(shot.source, oracle.ricker(n, dt))], shot.receivers, u0=u0, um1=u0)
+    el.append(time.perf_counter() - t)
+per = (el[1] - el[0]) / {nsteps}
+print(json.dumps({{"pts_per_s": float(np.prod(shot.shape)) / per, "steps": {nsteps}, "s": el[1] - el[0]}}))
+"""
+
+
+def _oracle_one_thread(workload: str, nsteps: int):
+    import subprocess
+
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    code = _ORACLE_CHILD.format(root=ROOT, workload=workload, nsteps=nsteps)
+    res = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=600)
+    if res.returncode != 0:
+        log(f"cpu baseline (1 thread) failed: {res.stderr[-400:]}")
+        return None
+    return json.loads(res.stdout.strip().splitlines()[-1])
+
+
 def run_cpu_baseline(workload: str = DEFAULT_WORKLOAD, budget_s: float = 15.0):
     """The FP64 oracle on the host cores, on a bounded sample of the same workload: the
-    full grid and velocity model, a few time steps (throughput per step is constant)."""
+    full grid and velocity model, a few time steps (throughput per step is constant);
+    then the same on one thread (one step), in a child process."""
     import numpy as np
 
     import oracle
@@ -413,10 +465,19 @@ def run_cpu_baseline(workload: str = DEFAULT_WORKLOAD, budget_s: float = 15.0):
     pts = int(np.prod(shot.shape))
     val = pts * nsteps / el / 1e9
     grid = "x".join(str(n) for n in shot.shape[::-1])
-    log(f"cpu baseline: {val:.3f} Gpts/s ({nsteps} steps of {grid} FP64 in {el:.1f} s, {cores} threads)")
+    model = cpu_model()
+    log(f"cpu baseline: {val:.3f} Gpts/s ({nsteps} steps of {grid} FP64 in {el:.1f} s, {cores} threads, {model})")
+    one = _oracle_one_thread(workload, 1)
+    if one is not None:
+        log(f"cpu baseline, 1 thread: {one['pts_per_s'] / 1e9:.4f} Gpts/s ({one['steps']} step in {one['s']:.1f} s)")
     return {"value": round(val, 4), "unit": "Gpts/s", "cores": cores, "kind": "oracle",
+            "cpu_model": model, "host_cpus_visible": os.cpu_count(),
+            "one_thread": None if one is None else {"value": round(one["pts_per_s"] / 1e9, 5), "unit": "Gpts/s",
+                                                    "steps": one["steps"], "wall_s": round(one["s"], 2)},
             "sample": f"FP64 oracle, full {grid} grid of the same workload ({velocity_label(shot)}), r={shot.r}, "
-                      f"{nsteps} time steps ({el:.1f} s wall)"}
+                      f"{nsteps} time steps ({el:.1f} s wall) on {cores} threads; the one-thread figure is the "
+                      f"difference of a 2-step and a 1-step run of the same grid in a child process with "
+                      f"OMP_NUM_THREADS=1"}
 
 
 def run_gradient():
@@ -552,15 +613,9 @@ def serving_requests(nreq=256, rate=20.0, sides=SERVING_SIDES):
     return reqs
 
 
-def serve_both(reqs, budget_gib, sequential, label):
-    """One trace through the continuous-batching server, then (optionally) one shot at a
-    time, on the same GPU."""
-    from paper_1410_1387_amd.serving import ShotServer, run_sequential, summarize
+def _serving_stats(srv, res, wall, budget_gib):
+    from paper_1410_1387_amd.serving import summarize
 
-    srv = ShotServer(r=4, dtype="f32", budget_bytes=budget_gib << 30, max_shots=64, chunk=16)
-    t0 = time.perf_counter()
-    res = srv.serve_trace(reqs)
-    wall = time.perf_counter() - t0
     st = summarize(res)
     st.update({"wall_s": round(wall, 2), "budget_gib": budget_gib, "chunk_steps": 16,
                "max_resident_shots": srv.stats["max_resident_shots"], "fill_points": srv.fill_points,
@@ -569,27 +624,61 @@ def serve_both(reqs, budget_gib, sequential, label):
                "batched_chunks": srv.stats["chunks"], "membership_changes": srv.stats["membership_changes"],
                "gpu_busy_s": round(srv.stats["gpu_busy_s"], 2), "host_admission_s": round(srv.stats["admit_s"], 2),
                "gpts_per_s_while_busy": round(srv.stats["chunk_points"] / max(srv.stats["gpu_busy_s"], 1e-9) / 1e9, 1)})
-    log(f"serving {label} (continuous batching): {st['gpts_per_s']:.1f} Gpts/s, makespan {st['makespan_s']:.2f} s, "
-        f"p50 {st['p50_latency_s']:.2f} s, p99 {st['p99_latency_s']:.2f} s, max resident {st['max_resident_shots']}")
-    out = {"batched": st}
-    if sequential:
-        s1 = summarize(run_sequential(reqs))
-        log(f"serving {label} (one at a time): {s1['gpts_per_s']:.1f} Gpts/s, makespan {s1['makespan_s']:.2f} s, "
-            f"p50 {s1['p50_latency_s']:.2f} s, p99 {s1['p99_latency_s']:.2f} s")
-        out["one_at_a_time"] = s1
-        out["throughput_ratio"] = round(st["gpts_per_s"] / s1["gpts_per_s"], 3) if s1["gpts_per_s"] else None
+    return st
+
+
+def _median(xs):
+    ys = sorted(xs)
+    n = len(ys)
+    return ys[n // 2] if n % 2 else 0.5 * (ys[n // 2 - 1] + ys[n // 2])
+
+
+def serve_both(reqs, budget_gib, label, pairs=3):
+    """One trace served `pairs` times with continuous batching (A) and `pairs` times one shot
+    at a time (B) on the same GPU, interleaved A B B A A B ... so that drift of the box's
+    clocks and temperature falls on both modes alike.  Reports every run, the median of each
+    mode and the per-pair throughput ratios A / B (median, min, max)."""
+    from paper_1410_1387_amd.serving import ShotServer, run_sequential, summarize
+
+    runs = {"batched": [], "one_at_a_time": []}
+    order = []
+    for k in range(pairs):
+        order += ["batched", "one_at_a_time"] if k % 2 == 0 else ["one_at_a_time", "batched"]
+    for mode in order:
+        if mode == "batched":
+            srv = ShotServer(r=4, dtype="f32", budget_bytes=budget_gib << 30, max_shots=64, chunk=16)
+            t0 = time.perf_counter()
+            res = srv.serve_trace(reqs)
+            st = _serving_stats(srv, res, time.perf_counter() - t0, budget_gib)
+        else:
+            st = summarize(run_sequential(reqs))
+        runs[mode].append(st)
+        log(f"serving {label} ({mode.replace('_', ' ')}, run {len(runs[mode])}): {st['gpts_per_s']:.1f} Gpts/s, "
+            f"makespan {st['makespan_s']:.2f} s, p50 {st['p50_latency_s']:.2f} s, p99 {st['p99_latency_s']:.2f} s")
+    ratios = [a["gpts_per_s"] / b["gpts_per_s"] for a, b in zip(runs["batched"], runs["one_at_a_time"])
+              if b["gpts_per_s"] > 0]
+    out = {"pairs": pairs, "order": order, "runs": runs}
+    for mode, rs in runs.items():
+        out[mode] = {key: round(_median([r[key] for r in rs]), 4)
+                     for key in ("gpts_per_s", "p50_latency_s", "p99_latency_s", "makespan_s")}
+        out[mode]["completed"] = min(r["completed"] for r in rs)
+        out[mode]["requests"] = rs[0]["requests"]
+    out["throughput_ratio"] = {"median": round(_median(ratios), 4), "min": round(min(ratios), 4),
+                               "max": round(max(ratios), 4), "per_pair": [round(x, 4) for x in ratios]}
+    log(f"serving {label}: batched / one at a time = {out['throughput_ratio']['median']:.3f} "
+        f"(pairs {', '.join(f'{x:.3f}' for x in ratios)})")
     return out
 
 
-def run_serving(nreq=256, budget_gib=96, sequential=True):
+def run_serving(nreq=256, budget_gib=96, pairs=3):
     """The serving trace (sides 128-400 at 20 req/s), and a trace of small shots (sides
     64-160, arriving at 400 req/s so that the GPU, not the arrivals, sets the pace), each
-    served with continuous batching and one shot at a time."""
+    served with continuous batching and one shot at a time in interleaved pairs."""
     out = {"workload": f"serving_{nreq}req_poisson20_sides128-400_r4_fp32"}
-    out.update(serve_both(serving_requests(nreq), budget_gib, sequential, "sides 128-400"))
+    out.update(serve_both(serving_requests(nreq), budget_gib, "sides 128-400", pairs))
     small = {"workload": f"serving_{nreq}req_poisson400_sides64-160_r4_fp32"}
-    small.update(serve_both(serving_requests(nreq, rate=400.0, sides=SMALL_SIDES), budget_gib, sequential,
-                            "sides 64-160"))
+    small.update(serve_both(serving_requests(nreq, rate=400.0, sides=SMALL_SIDES), budget_gib, "sides 64-160",
+                            pairs))
     out["small_shots"] = small
     return out
 
@@ -600,8 +689,10 @@ def main():
     ap.add_argument("--steps", type=int, default=3, help="timed shots (each a whole shot of the workload)")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--gradient", action="store_true", help="also time the adjoint gradient workload")
-    ap.add_argument("--serving", action="store_true", help="also run the shot-serving workload")
+    ap.add_argument("--no-gradient", action="store_true", help="skip the adjoint gradient workload")
+    ap.add_argument("--no-serving", action="store_true", help="skip the shot-serving workload")
+    ap.add_argument("--serving-pairs", type=int, default=3,
+                    help="interleaved (batched, one-at-a-time) runs of each serving trace")
     ap.add_argument("--copy-probe", action="store_true", help="run a 1 GiB copy (counter scaling reference)")
     ap.add_argument("--no-vti", action="store_true", help="skip the VTI propagator section")
     ap.add_argument("--summarize-prof", metavar="DIR", help="summarize rocprofv3 CSV output and exit")
@@ -652,10 +743,15 @@ def main():
     default = args.workload == DEFAULT_WORKLOAD
     if default and not args.no_vti:
         out["vti"] = run_vti(args)
-    if default and args.gradient:
+    if default and not args.no_gradient:
         out["gradient"] = run_gradient()
-    if default and args.serving:
-        out["serving"] = run_serving()
+    if default and not args.no_serving:
+        sv = run_serving(pairs=max(1, args.serving_pairs))
+        out["serving"] = sv
+        # the metric's latency half: the main serving trace, continuous batching, median run
+        out["p50_latency_s"] = sv["batched"]["p50_latency_s"]
+        out["p99_latency_s"] = sv["batched"]["p99_latency_s"]
+        out["serving_vs_one_at_a_time"] = sv["throughput_ratio"]["median"]
     out["cpu_baseline"] = None if args.no_cpu else run_cpu_baseline(args.workload)
     print(json.dumps(out), flush=True)
 

@@ -95,10 +95,17 @@ class _Live:
     """A shot resident on the GPU."""
 
     def __init__(self, req: ShotRequest, ctx: int, tensors: list, traces: torch.Tensor, footprint: int,
-                 npoints: int, arrival: float, admitted: float, future: cf.Future):
+                 npoints: int, arrival: float, admitted: float, future: cf.Future, kernel: str = ""):
         self.req, self.ctx, self.tensors, self.traces = req, ctx, tensors, traces
         self.footprint, self.npoints = footprint, npoints
         self.arrival, self.admitted, self.future = arrival, admitted, future
+        self.kernel = kernel  # shots batch only with shots of the same stencil kernel
+
+
+def kernel_of(ctx: int) -> str:
+    """The stencil kernel (tile shape) a context steps with: its configuration name without
+    the per-shot z chunking and grid size."""
+    return F.fd_kernel_config(ctx).split(", zchunk")[0]
 
 
 def shot_footprint(shape, nsteps: int, nrec: int, r: int, dtype: str) -> int:
@@ -320,7 +327,8 @@ class ShotServer:
                         t.record_stream(bstream)
                     self.stats["admit_s"] += time.perf_counter() - t_adm
                     self.stats["max_admission_bytes"] = max(self.stats["max_admission_bytes"], used + peak)
-                    active.append(_Live(req, ctx, tensors, traces, fp, npts, arrival, self.now(), fut))
+                    active.append(_Live(req, ctx, tensors, traces, fp, npts, arrival, self.now(), fut,
+                                        kernel_of(ctx)))
                     used += fp
                     dirty = True
                 self.stats["max_resident_bytes"] = max(self.stats["max_resident_bytes"], used)
@@ -375,9 +383,14 @@ class ShotServer:
             F.fd_batch_destroy(batch)
 
     def _window(self, active: list) -> list:
-        """The oldest unfinished resident shots, in admission order, until their grid points
-        per step reach fill_points (at least one shot)."""
+        """The oldest unfinished resident shots, in admission order, that use the oldest
+        one's stencil kernel (one launch runs one kernel; the library picks a shot's tile
+        shape from its grid), until their grid points per step reach fill_points (at least
+        one shot).  The oldest shot always steps, so no shot waits for ever."""
         live = [s for s in active if not s.future.done() and not getattr(s, "_queued_done", False)]
+        if not live:
+            return []
+        live = [s for s in live if s.kernel == live[0].kernel]
         if self.fill_points is None:
             return live
         out, pts = [], 0

@@ -184,21 +184,26 @@ def test_server_budget_backpressure():
     say(f"budget {budget} B")
     srv = ShotServer(r=4, chunk=8, max_shots=8, budget_bytes=budget)
     torch.cuda.synchronize()
-    base = torch.cuda.memory_allocated()
+    # bytes the program asked the allocator for: the allocator's own bookkeeping rounds a
+    # reused cached block up by as much as 1 MiB (it does not split off a small remainder),
+    # which is not memory the server requested
+    key = "requested_bytes.all.peak"
+    assert key in torch.cuda.memory_stats(), "torch does not report requested bytes"
+    base = torch.cuda.memory_stats()["requested_bytes.all.current"]
     torch.cuda.reset_peak_memory_stats()
     res = {r.rid: r for r in srv.serve_trace(reqs, realtime=False)}
     torch.cuda.synchronize()
-    peak = torch.cuda.max_memory_allocated() - base
+    peak = torch.cuda.memory_stats()[key] - base
     seq = {r.rid: r for r in run_sequential(reqs, realtime=False)}
     assert all(r.status == "ok" for r in res.values())
     assert srv.stats["max_resident_bytes"] <= budget
     assert srv.stats["max_admission_bytes"] <= budget
-    # the device memory the server really allocated, staged models included, stays within the
-    # budget plus its own batch table, the traces it has already handed back (they belong to
-    # the caller once a shot completes) and the allocator's 512-byte rounding of each tensor
+    # the device memory the server really requested, staged models included, stays within the
+    # budget plus its own batch table and the traces it has already handed back (they belong
+    # to the caller once a shot completes)
     handed_back = sum(r.traces.numel() * r.traces.element_size() for r in res.values())
     slack = F.fd_batch_workspace_bytes(8) + 64 * 1024
-    say(f"peak device allocation {peak} B against budget {budget} B (+ {handed_back} B of returned traces)")
+    say(f"peak requested device memory {peak} B against budget {budget} B (+ {handed_back} B of returned traces)")
     assert peak <= budget + handed_back + slack
     for rid in res:
         assert np.array_equal(res[rid].traces.cpu().numpy(), seq[rid].traces.cpu().numpy())

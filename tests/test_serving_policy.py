@@ -60,3 +60,14 @@ def test_default_window_fits_the_last_level_cache():
     assert 12 * fill <= 256 * 10 ** 6
     # and a 256^3 shot fills it alone
     assert 256 ** 3 >= fill
+
+
+def test_window_keeps_to_one_kernel():
+    # one launch runs one stencil kernel: shots whose grid got another tile shape wait for
+    # a window led by a shot of their own kind
+    a, b, c, d = live(64), live(64), live(64), live(64)
+    a.kernel, b.kernel, c.kernel, d.kernel = "k1", "k2", "k1", "k2"
+    assert window(16_000_000, [a, b, c, d]) == [a, c]
+    assert window(None, [a, b, c, d]) == [a, c]
+    a.future.set_result(None)
+    assert window(16_000_000, [a, b, c, d]) == [b, d]
