@@ -330,6 +330,12 @@ const char *fd_kernel_config(const fd_ctx *ctx);
  * zchunk > 0 overrides the planes each workgroup marches in z. */
 int fd_set_tuning(fd_dtype dtype, int r, int ndim, int config, int zchunk);
 
+/* The adjoint kernel's tile shape for contexts created afterwards with this (dtype, r,
+ * ndim): config indexes the registered adjoint tiles (0 = the default).  Process-wide,
+ * thread-safe; a tuning knob like fd_set_tuning.  Errors:
+ * FD_E_INVAL (no adjoint kernel for dtype/r/ndim), FD_E_RANGE (config). */
+int fd_set_adj_tuning(fd_dtype dtype, int r, int ndim, int config);
+
 const char *fd_last_error(void);
 
 /* ================================================================= VTI propagator

@@ -65,10 +65,4 @@ const AdjEntry *adj_configs_f32(int r, int ndim, int *count)
     }
 }
 
-const AdjEntry *adj_config_f32(int r, int ndim)
-{
-    int n = 0;
-    return adj_configs_f32(r, ndim, &n);
-}
-
 }  // namespace fdw

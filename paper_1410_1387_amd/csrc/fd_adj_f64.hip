@@ -60,10 +60,4 @@ const AdjEntry *adj_configs_f64(int r, int ndim, int *count)
     }
 }
 
-const AdjEntry *adj_config_f64(int r, int ndim)
-{
-    int n = 0;
-    return adj_configs_f64(r, ndim, &n);
-}
-
 }  // namespace fdw

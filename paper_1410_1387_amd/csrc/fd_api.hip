@@ -156,9 +156,19 @@ const FwdEntry *fwd_table(fd_dtype dt, int r, int ndim, int *count)
     return dt == FD_F32 ? fwd_configs_f32(r, ndim, count) : fwd_configs_f64(r, ndim, count);
 }
 
-const AdjEntry *adj_table(fd_dtype dt, int r, int ndim)
+const AdjEntry *adj_table(fd_dtype dt, int r, int ndim, int *count)
 {
-    return dt == FD_F32 ? adj_config_f32(r, ndim) : adj_config_f64(r, ndim);
+    return dt == FD_F32 ? adj_configs_f32(r, ndim, count) : adj_configs_f64(r, ndim, count);
+}
+std::map<std::tuple<int, int, int>, int> g_adj_tuning;
+
+// The last x tile and its halo (at most 8 points) stay inside the padded row, which
+// holds align_up(nx, 256) + 16 points after the interior start: always true of tiles
+// whose width divides 256.
+bool tile_fits(const FwdEntry &e, const Layout &L)
+{
+    const int64_t tiles_x = (L.knx + e.bx - 1) / e.bx;
+    return tiles_x * e.bx + 8 <= align_up(L.knx, 256) + 16;
 }
 
 }  // namespace
@@ -394,6 +404,20 @@ extern "C" int fd_set_tuning(fd_dtype dtype, int r, int ndim, int config, int zc
 
 // ------------------------------------------------------------------ lifecycle
 
+extern "C" int fd_set_adj_tuning(fd_dtype dtype, int r, int ndim, int config)
+{
+    int count = 0;
+    const AdjEntry *tab = (dtype == FD_F32 || dtype == FD_F64) ? adj_table(dtype, r, ndim, &count) : nullptr;
+    if (!tab || count == 0) return fail(FD_E_INVAL, "fd_set_adj_tuning: bad dtype/r/ndim");
+    if (config < 0 || config >= count) return fail(FD_E_RANGE, "fd_set_adj_tuning: config %d of %d", config, count);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (config == 0)
+        g_adj_tuning.erase(std::make_tuple((int)dtype, r, ndim));
+    else
+        g_adj_tuning[std::make_tuple((int)dtype, r, ndim)] = config;
+    return FD_OK;
+}
+
 extern "C" int fd_create(fd_ctx **out, const fd_grid *g, int r, double h, double dt, const void *velocity,
                          fd_dtype dtype, fd_bc bc, void *workspace, size_t ws_bytes, int64_t max_sources,
                          int64_t max_receivers, void *stream)
@@ -417,16 +441,24 @@ extern "C" int fd_create(fd_ctx **out, const fd_grid *g, int r, double h, double
                 return fail(FD_E_INVAL, "fd_create: periodic grid must have at least r points per axis");
     }
 
-    int count = 0;
+    int count = 0, acount = 0;
     const FwdEntry *tab = fwd_table(dtype, r, g->ndim, &count);
-    const AdjEntry *ka = adj_table(dtype, r, g->ndim);
-    if (!tab || count == 0 || !ka) return fail(FD_E_INVAL, "fd_create: no kernel for this dtype/r/ndim");
+    const AdjEntry *atab = adj_table(dtype, r, g->ndim, &acount);
+    if (!tab || count == 0 || !atab || acount == 0) return fail(FD_E_INVAL, "fd_create: no kernel for this dtype/r/ndim");
     Tuning tu{0, 0};
+    int acfg = 0;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tuning.find(std::make_tuple((int)dtype, r, (int)g->ndim));
         if (it != g_tuning.end()) tu = it->second;
+        auto ia = g_adj_tuning.find(std::make_tuple((int)dtype, r, (int)g->ndim));
+        if (ia != g_adj_tuning.end()) acfg = ia->second;
     }
+    const AdjEntry *ka = &atab[acfg];
+
+    if (!tile_fits(tab[tu.config], L))
+        return fail(FD_E_INVAL, "fd_create: tile %s does not fit a row of %lld points", tab[tu.config].name,
+                    (long long)L.knx);
 
     fd_ctx *c = new fd_ctx();
     c->g = *g;

@@ -934,8 +934,6 @@ AdjEntry adj_entry(const char *name)
 // Implemented in the per-dtype translation units.
 const FwdEntry *fwd_configs_f32(int r, int ndim, int *count);
 const FwdEntry *fwd_configs_f64(int r, int ndim, int *count);
-const AdjEntry *adj_config_f32(int r, int ndim);
-const AdjEntry *adj_config_f64(int r, int ndim);
 const AdjEntry *adj_configs_f32(int r, int ndim, int *count);
 const AdjEntry *adj_configs_f64(int r, int ndim, int *count);
 

@@ -112,8 +112,7 @@ def adj_file(T, d3, d3_big_r=None):
             out += (f"    case {R * 10 + nd}: *count = (int)(sizeof(a{nd}_r{R}) / sizeof(AdjEntry)); "
                     f"return a{nd}_r{R};\n")
     out += "    default: *count = 0; return nullptr;\n    }\n}\n\n"
-    out += ("const AdjEntry *adj_config_" + tag + "(int r, int ndim)\n{\n    int n = 0;\n"
-            "    return adj_configs_" + tag + "(r, ndim, &n);\n}\n\n}  // namespace fdw\n")
+    out += "}  // namespace fdw\n"
     with open(os.path.join(HERE, f"fd_adj_{tag}.hip"), "w") as f:
         f.write(out)
 

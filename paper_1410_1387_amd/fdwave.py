@@ -33,7 +33,7 @@ EXPORTS = [
     "fd_set_stream", "fd_inject", "fd_clear_sources", "fd_set_damping", "fd_record", "fd_ricker", "fd_step", "fd_sync",
     "fd_get_step", "fd_get_state", "fd_set_time_blocking", "fd_set_state", "fd_step_explicit", "fd_adjoint_segment",
     "fd_gradient_finish", "fd_batch_workspace_bytes", "fd_batch_create", "fd_batch_create_noalloc", "fd_batch_destroy",
-    "fd_batch_set", "fd_batch_step", "fd_copy_probe", "fd_stream_probe", "fd_check_finite", "fd_kernel_config", "fd_set_tuning",
+    "fd_batch_set", "fd_batch_step", "fd_copy_probe", "fd_stream_probe", "fd_check_finite", "fd_kernel_config", "fd_set_tuning", "fd_set_adj_tuning",
     "fd_last_error",
     "fd_vti_z_weights", "fd_vti_dt_max", "fd_vti_workspace_bytes", "fd_vti_create", "fd_vti_destroy",
     "fd_vti_inject", "fd_vti_record", "fd_vti_step", "fd_vti_sync", "fd_vti_get_step", "fd_vti_get_state",
@@ -103,6 +103,7 @@ def lib():
             "fd_check_finite": (ctypes.c_int, [P, ctypes.POINTER(ctypes.c_int)]),
             "fd_kernel_config": (ctypes.c_char_p, [P]),
             "fd_set_tuning": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+            "fd_set_adj_tuning": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
             "fd_last_error": (ctypes.c_char_p, []),
             "fd_vti_z_weights": (ctypes.c_int, [ctypes.POINTER(D), I64, ctypes.c_int, ctypes.POINTER(D)]),
             "fd_vti_dt_max": (D, [ctypes.c_int, ctypes.c_int, D, ctypes.POINTER(D), I64, D, D, D]),
@@ -345,6 +346,10 @@ def fd_kernel_config(ctx: int) -> str:
 
 def fd_set_tuning(dtype, r: int, ndim: int, config: int, zchunk: int = 0):
     _check(lib().fd_set_tuning(dtype_code(dtype), r, ndim, config, zchunk), "fd_set_tuning")
+
+
+def fd_set_adj_tuning(dtype, r: int, ndim: int, config: int):
+    _check(lib().fd_set_adj_tuning(dtype_code(dtype), r, ndim, config), "fd_set_adj_tuning")
 
 
 # ------------------------------------------------------------------ VTI propagator

@@ -100,9 +100,18 @@ def test_layout_sizes(F):
 
 
 def test_tuning_table_accepts_known_configs(F):
-    for cfg in range(7):
+    for cfg in range(8):
         F.fd_set_tuning("f32", 4, 3, cfg)
     F.fd_set_tuning("f32", 4, 3, 0)  # restore the default
+    for cfg in range(5):
+        F.fd_set_adj_tuning("f32", 4, 3, cfg)
+    F.fd_set_adj_tuning("f32", 4, 3, 0)
+    with pytest.raises(F.FdError) as e:
+        F.fd_set_adj_tuning("f32", 4, 3, 99)
+    assert e.value.status == F.FD_E_RANGE
+    with pytest.raises(F.FdError) as e:
+        F.fd_set_adj_tuning("f32", 0, 3, 0)
+    assert e.value.status == F.FD_E_INVAL
 
 
 # ----------------------------------------------------------------------------- VTI host entry points

@@ -78,6 +78,27 @@ def test_checkpoint_interval_bitwise(oracle_mod):
         assert np.array_equal(gk, grads[0])
 
 
+@pytest.mark.parametrize("r,ncfg", [(4, 5), (8, 2)])
+def test_adjoint_tile_shapes_bitwise(oracle_mod, r, ncfg):
+    # every registered adjoint tile runs the same per-point arithmetic, so the gradient
+    # is bitwise the same whatever the tile shape (a difference exposes a race or an
+    # indexing error); the grid is ragged against every tile
+    from paper_1410_1387_amd import fdwave as F
+
+    v, pb, obs = _problem(oracle_mod, (23, 37, 45), r, 40, 9, "f32", seed=11)
+    grads = []
+    try:
+        for cfg in range(ncfg):
+            F.fd_set_adj_tuning("f32", r, 3, cfg)
+            say(f"adjoint tile config {cfg}, r={r}")
+            grads.append(_gpu_gradient(v, pb, obs)[1])
+    finally:
+        F.fd_set_adj_tuning("f32", r, 3, 0)
+    assert np.linalg.norm(grads[0]) > 0
+    for cfg, gk in enumerate(grads[1:], 1):
+        assert np.array_equal(gk, grads[0]), cfg
+
+
 def test_gradient_linear_in_residual(oracle_mod):
     import torch
 
