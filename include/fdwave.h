@@ -183,9 +183,11 @@ int fd_step(fd_ctx *ctx, int64_t nsteps);
  * two-step launches (through aux and back, so the context's fields keep their roles) and
  * any remainder as single steps.  Periodic or damped contexts keep single steps.
  * config: index of the tile shape (0 = default).  aux = NULL disables.  On MI355X this
- * path moves 20 instead of 32 bytes per point and two steps but is latency-bound (one
- * workgroup per compute unit, two barriers per plane): 228 Gpts/s against 351 for single
- * steps at 512^3, so it is off unless enabled.  Errors:
+ * path moves 20 instead of 32 bytes per point and two steps but is slower than single
+ * steps (228 against 352 Gpts/s at 512^3): level 1 on the widened tile costs 80 instead
+ * of 59 vector instructions per point update, and the launch is latency-bound (one
+ * workgroup per compute unit, two barriers per plane).  It is off unless enabled and no
+ * benchmark figure uses it.  Errors:
  * FD_E_INVAL (no two-step kernel: 3-D FP32 with r = 4 only; misaligned aux), FD_E_RANGE
  * (config), FD_E_NOMEM (aux too small). */
 int fd_set_time_blocking(fd_ctx *ctx, void *aux, size_t aux_bytes, int config);

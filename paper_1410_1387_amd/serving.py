@@ -325,6 +325,10 @@ class ShotServer:
                         continue
                     for t in tensors + [traces]:  # written by batched kernels on bstream
                         t.record_stream(bstream)
+                    # set-up has finished on sstream (create synchronises it); from now on the
+                    # shot runs on the batch stream, so batched steps need no cross-stream
+                    # ordering and later set-ups on sstream never wait for a running chunk
+                    F.fd_set_stream(ctx, F.stream_ptr(bstream))
                     self.stats["admit_s"] += time.perf_counter() - t_adm
                     self.stats["max_admission_bytes"] = max(self.stats["max_admission_bytes"], used + peak)
                     active.append(_Live(req, ctx, tensors, traces, fp, npts, arrival, self.now(), fut,
