@@ -7,8 +7,10 @@
   start model, 2000 steps, checkpoints every 50): the FP32 GPU gradient against the
   oracle's checkpointed FP64 discrete adjoint, both given the oracle's FP64 residual
   (<= 1e-3) and end to end from FP64 observed data.
-* The 384^3 r = 8 smoothed-noise shot: FD_PARITY_C3_STEPS steps (default 300, the
-  stated 2000 when set) against the oracle.
+* The 384^3 r = 8 smoothed-noise shot, its stated 2000 steps (FD_PARITY_C3_STEPS sets
+  fewer), against the oracle.
+* The VTI benchmark workload's construction (layered vz, eps, delta; z spacing stretched
+  with depth; R_xy = 12, R_z = 8) at 128^3 for 400 steps, full fields and traces.
 
 The oracle runs in chunks and prints its progress outside pytest's capture, so a
 long run shows that it is moving.  Named to run after the other GPU files: these are
@@ -58,7 +60,7 @@ def test_c2_full_shot_vs_oracle(oracle_mod, progress):
 
 def test_c3_shot_vs_oracle(oracle_mod, progress):
     shot = workloads.c3_3d_noise()
-    T = int(os.environ.get("FD_PARITY_C3_STEPS", "300"))
+    T = int(os.environ.get("FD_PARITY_C3_STEPS", str(shot.nsteps)))
     assert 1 <= T <= shot.nsteps
     v = shot.velocity()
     dt = shot.courant * oracle_mod.dt_max(3, shot.r, shot.h, v.max())
@@ -67,12 +69,35 @@ def test_c3_shot_vs_oracle(oracle_mod, progress):
                   ricker=(shot.source, shot.f0, 1.5 / shot.f0), label=shot.name)
     wav = oracle_mod.ricker(T, dt, shot.f0)
     ref = oracle_forward_chunked(oracle_mod, v, shot.h, dt, shot.r, T, [(shot.source, wav)], shot.receivers,
-                                 progress)
+                                 progress, chunk=200)
     eu, ep = rel_l2(got["u"], ref["u"]), rel_l2(got["u_prev"], ref["u_prev"])
     et = rel_l2(got["traces"], ref["traces"])
     progress(f"{shot.name} x {T}: rel L2 u^T {eu:.2e} u^(T-1) {ep:.2e} traces {et:.2e} [{got['config']}]")
     assert np.linalg.norm(ref["u"]) > 0
     assert eu <= 1e-4 and ep <= 1e-4 and et <= 1e-4
+
+
+def test_vti_128_long_run_vs_oracle(oracle_mod, progress):
+    import dataclasses
+
+    from test_gpu_vti import run_vti_gpu
+
+    shot = dataclasses.replace(workloads.VtiShot(), n=128, nsteps=400)
+    vz, eps, delta = shot.models()
+    zc = shot.zc()
+    dt = shot.courant * oracle_mod.vti_dt_max(shot.rxy, shot.rz, shot.h, oracle_mod.z_weights(zc, shot.rz),
+                                              vz, eps, delta)
+    T, rec = shot.nsteps, shot.receivers()
+    src = [(shot.source, oracle_mod.ricker(T, dt, shot.f0), 1.0, 0.0)]
+    progress(f"VTI 128^3 rxy={shot.rxy} rz={shot.rz} x {T}: GPU FP32")
+    out = run_vti_gpu(vz, eps, delta, shot.h, zc, dt, shot.rxy, shot.rz, T, "f32", sources=src, receivers=rec)
+    progress("VTI 128^3: oracle")
+    ref = oracle_mod.vti_forward(vz, eps, delta, shot.h, dt, shot.rxy, shot.rz, T, zc=zc, sources=src,
+                                 receivers=rec)
+    errs = {f: rel_l2(out[f], ref[f]) for f in ("p", "p_prev", "q", "q_prev", "traces_p", "traces_q")}
+    progress(f"VTI 128^3 x {T}: " + ", ".join(f"{k} {v:.2e}" for k, v in errs.items()) + f" [{out['config']}]")
+    assert np.linalg.norm(ref["p"]) > 0
+    assert all(e <= 1e-4 for e in errs.values()), errs
 
 
 def test_c4_gradient_vs_oracle(oracle_mod, progress):
