@@ -327,9 +327,13 @@ int fd_stream_probe(const void *a, const void *b, void *c, size_t bytes, int blo
  * z-chunk and launch size. */
 const char *fd_kernel_config(const fd_ctx *ctx);
 
-/* Select a stencil tile configuration by index (0 = default) for contexts created
- * afterwards with this (dtype, r, ndim); returns FD_E_RANGE for an unknown index.
- * zchunk > 0 overrides the planes each workgroup marches in z. */
+/* Select a stencil tile configuration by index for contexts created afterwards with this
+ * (dtype, r, ndim); returns FD_E_RANGE for an unknown index.  zchunk > 0 overrides the
+ * planes each workgroup marches in z.  config = -1 restores the library's own choice,
+ * which is also what holds before any call: the default tile (index 0), or, for FP32 3-D
+ * radii <= 4 on grids whose default z chunks would be 16 to 63 planes long (256^3 and
+ * 320^3, say), the same tile built for four waves per SIMD (the last registered index).
+ * Results are bitwise the same whatever the tile. */
 int fd_set_tuning(fd_dtype dtype, int r, int ndim, int config, int zchunk);
 
 /* The adjoint kernel's tile shape for contexts created afterwards with this (dtype, r,

@@ -6,18 +6,21 @@
 namespace fdw {
 static const FwdEntry k3_r1[] = {
     fwd_entry<TileCfg<float, 1, 3, 16, 16, 1>>("f32 r1 3d tile 64x16 (256 thr, 1 row/thr)"),
+    fwd_entry<TileCfg<float, 1, 3, 16, 16, 1, 4, 4>>("f32 r1 3d tile 64x16 (256 thr, 1 row/thr, built for 4 waves/SIMD)", FWD_SMALL_GRID),
 };
 static const FwdEntry k2_r1[] = {
     fwd_entry<TileCfg<float, 1, 2, 64, 1, 1>>("f32 r1 2d tile 256x1 (64 thr, 1 row/thr)"),
 };
 static const FwdEntry k3_r2[] = {
     fwd_entry<TileCfg<float, 2, 3, 16, 16, 1>>("f32 r2 3d tile 64x16 (256 thr, 1 row/thr)"),
+    fwd_entry<TileCfg<float, 2, 3, 16, 16, 1, 4, 4>>("f32 r2 3d tile 64x16 (256 thr, 1 row/thr, built for 4 waves/SIMD)", FWD_SMALL_GRID),
 };
 static const FwdEntry k2_r2[] = {
     fwd_entry<TileCfg<float, 2, 2, 64, 1, 1>>("f32 r2 2d tile 256x1 (64 thr, 1 row/thr)"),
 };
 static const FwdEntry k3_r3[] = {
     fwd_entry<TileCfg<float, 3, 3, 16, 16, 1>>("f32 r3 3d tile 64x16 (256 thr, 1 row/thr)"),
+    fwd_entry<TileCfg<float, 3, 3, 16, 16, 1, 4, 4>>("f32 r3 3d tile 64x16 (256 thr, 1 row/thr, built for 4 waves/SIMD)", FWD_SMALL_GRID),
 };
 static const FwdEntry k2_r3[] = {
     fwd_entry<TileCfg<float, 3, 2, 64, 1, 1>>("f32 r3 2d tile 256x1 (64 thr, 1 row/thr)"),
@@ -31,6 +34,7 @@ static const FwdEntry k3_r4[] = {
     fwd_entry<TileCfg<float, 4, 3, 32, 16, 2>>("f32 r4 3d tile 128x32 (512 thr, 2 row/thr)"),
     fwd_entry<TileCfg<float, 4, 3, 8, 32, 2>>("f32 r4 3d tile 32x64 (256 thr, 2 row/thr)"),
     fwd_entry<TileCfg<float, 4, 3, 8, 32, 1>>("f32 r4 3d tile 32x32 (256 thr, 1 row/thr)"),
+    fwd_entry<TileCfg<float, 4, 3, 16, 16, 1, 4, 4>>("f32 r4 3d tile 64x16 (256 thr, 1 row/thr, built for 4 waves/SIMD)", FWD_SMALL_GRID),
 };
 static const FwdEntry k2_r4[] = {
     fwd_entry<TileCfg<float, 4, 2, 64, 1, 1>>("f32 r4 2d tile 256x1 (64 thr, 1 row/thr)"),

@@ -184,9 +184,13 @@ __device__ __forceinline__ int lower_bound_z(const Event *ev, int lo, int hi, in
 
 // ------------------------------------------------------------------ tile configuration
 
-template <typename T, int R_, int NDIM_, int TXN_, int TYN_, int EY_, int VEC_ = V16<T>::N>
+template <typename T, int R_, int NDIM_, int TXN_, int TYN_, int EY_, int VEC_ = V16<T>::N, int OCC_ = 0>
 struct TileCfg {
     typedef T type;
+    // OCC > 0: the forward kernel is built for OCC waves per SIMD (the compiler keeps to
+    // the matching register budget), keeps one set of prefetch registers instead of two
+    // and, for OCC >= 4, fetches the early halo one plane later (a smaller LDS ring)
+    static constexpr int OCC = OCC_;
     static constexpr int R = R_;
     static constexpr int NDIM = NDIM_;
     static constexpr int TXN = TXN_;                       // threads along x
@@ -210,7 +214,7 @@ struct TileCfg {
     static constexpr int YR = EY + 2 * HY;                 // rows a thread touches along y
     // forward kernel: halo fetched HOFF planes ahead into a ring of NB LDS plane buffers
     // (early halo for R <= 4; larger radii would need too much LDS)
-    static constexpr int HOFF = (R <= 4) ? R : 0;
+    static constexpr int HOFF = (R <= 4) ? (OCC_ >= 4 ? R - 1 : R) : 0;
     static constexpr int NB = HOFF + 2;
     static_assert(256 % BX == 0 && 64 % BY == 0, "tile must divide the layout alignment");
 };
@@ -348,8 +352,12 @@ __device__ __forceinline__ void fwd_tile(const ShotDesc &s, const typename C::ty
 #pragma unroll
     for (int k = 0; k < HPT; ++k) hob[k] = (uint32_t)((g.hoff[k] - (int64_t)R * pxy) * (int64_t)sizeof(T));
 
+    // LEAN: one register set for the u^{n-1}, c and halo prefetches (the next plane's
+    // values are loaded into it once the current plane is done with it) instead of two
+    constexpr bool LEAN = C::OCC > 0;
+    constexpr int NSET = LEAN ? 1 : 2;
     T q[P][EY][VEC];
-    T pv[2][EY][VEC], cv[2][EY][VEC], hv[2][HPT][VEC];
+    T pv[NSET][EY][VEC], cv[NSET][EY][VEC], hv[NSET][HPT][VEC];
 
     // prologue: planes z0-R .. z0+R into slots 0 .. 2R; u^{n-1} and c of plane z0 into
     // set 0; halos of planes z0 .. z0+HOFF-1 straight into their LDS buffers and the
@@ -411,7 +419,7 @@ __device__ __forceinline__ void fwd_tile(const ShotDesc &s, const typename C::ty
     for (int zb = g.z0; zb < g.z1; zb += 2) {
         static_for<2>([&](auto st_) __attribute__((always_inline)) {
             constexpr int st = decltype(st_)::value;
-            constexpr int cs = st & 1, ns = cs ^ 1;
+            constexpr int cs = LEAN ? 0 : (st & 1), ns = LEAN ? 0 : (cs ^ 1);
             constexpr int tail = 2 * R + 1;  // slot receiving plane z+R+1
             constexpr int ctr = R;           // slot of plane z
             const int z = zb + st;
@@ -420,13 +428,13 @@ __device__ __forceinline__ void fwd_tile(const ShotDesc &s, const typename C::ty
 #pragma unroll
                 for (int e = 0; e < EY; ++e) {
                     if (g.lin[e]) vld(q[tail][e], plane_at(cur, pxy, z + 1 + 2 * R, ob[e]));
-                    if (g.rin[e]) {
+                    if (!LEAN && g.rin[e]) {
                         vld_nt(pv[ns][e], plane_at(prev, pxy, z + 1 + R, ob[e]));
                         vld_nt(cv[ns][e], plane_at(cc, pxy, z + 1 + R, ob[e]));
                     }
                 }
             }
-            if (z + 1 + HOFF < g.z1) {
+            if (!LEAN && z + 1 + HOFF < g.z1) {
 #pragma unroll
                 for (int k = 0; k < HPT; ++k)
                     if (g.hval[k]) vld(hv[ns][k], plane_at(cur, pxy, z + 1 + HOFF + R, hob[k]));
@@ -441,6 +449,11 @@ __device__ __forceinline__ void fwd_tile(const ShotDesc &s, const typename C::ty
 #pragma unroll
                 for (int k = 0; k < HPT; ++k)
                     if (g.hval[k]) vst(LH + g.hl[k], hv[cs][k]);
+            }
+            if (LEAN && z + 1 + HOFF < g.z1) {  // the next halo, into the registers just staged
+#pragma unroll
+                for (int k = 0; k < HPT; ++k)
+                    if (g.hval[k]) vld(hv[0][k], plane_at(cur, pxy, z + 1 + HOFF + R, hob[k]));
             }
             __syncthreads();
 
@@ -504,6 +517,15 @@ __device__ __forceinline__ void fwd_tile(const ShotDesc &s, const typename C::ty
                 }
             }
 
+            if (LEAN && z + 1 < g.z1) {  // u^{n-1} and c of the next plane, into the registers just used
+#pragma unroll
+                for (int e = 0; e < EY; ++e)
+                    if (g.rin[e]) {
+                        vld_nt(pv[0][e], plane_at(prev, pxy, z + 1 + R, ob[e]));
+                        vld_nt(cv[0][e], plane_at(cc, pxy, z + 1 + R, ob[e]));
+                    }
+            }
+
             // fused sources (added before the store) and receivers (recorded after them)
             if (z == nev) {
                 int nxt = 0x7fffffff;
@@ -562,7 +584,24 @@ __device__ __forceinline__ void fwd_tile(const ShotDesc &s, const typename C::ty
 }
 
 template <class C>
+__device__ __forceinline__ void fwd_body(LaunchArgs a);
+
+template <class C>
 __global__ __launch_bounds__(C::NT) void fwd_kernel(LaunchArgs a)
+{
+    fwd_body<C>(a);
+}
+
+// the same step built for C::OCC waves per SIMD
+template <class C>
+__global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(C::OCC > 0 ? C::OCC : 1)))
+void fwd_kernel_occ(LaunchArgs a)
+{
+    fwd_body<C>(a);
+}
+
+template <class C>
+__device__ __forceinline__ void fwd_body(LaunchArgs a)
 {
     typedef typename C::type T;
     __shared__ __attribute__((aligned(16))) T lds[C::NB * C::LDS];
@@ -893,11 +932,17 @@ __global__ __launch_bounds__(C::NT) void adj_kernel(AdjArgs a)
 
 // ------------------------------------------------------------------ registry
 
+// Roles of a forward tile entry: an option for fd_set_tuning, or the one the library
+// takes by itself for grids whose default z chunk is short (many short chunks: more
+// resident waves pay off there).
+enum { FWD_OPTION = 0, FWD_SMALL_GRID = 1 };
+
 struct FwdEntry {
     const char *name;
     int bx, by, nt;
     void (*launch)(const LaunchArgs &, int nwg, hipStream_t);
     const void *kernel;  // the __global__ function (for occupancy queries)
+    int role;
 };
 
 struct AdjEntry {
@@ -910,7 +955,10 @@ struct AdjEntry {
 template <class C>
 void launch_fwd(const LaunchArgs &a, int nwg, hipStream_t st)
 {
-    hipLaunchKernelGGL(fwd_kernel<C>, dim3(nwg), dim3(C::NT), 0, st, a);
+    if constexpr (C::OCC > 0)
+        hipLaunchKernelGGL(fwd_kernel_occ<C>, dim3(nwg), dim3(C::NT), 0, st, a);
+    else
+        hipLaunchKernelGGL(fwd_kernel<C>, dim3(nwg), dim3(C::NT), 0, st, a);
 }
 
 template <class C>
@@ -920,9 +968,14 @@ void launch_adj(const AdjArgs &a, int nwg, hipStream_t st)
 }
 
 template <class C>
-FwdEntry fwd_entry(const char *name)
+FwdEntry fwd_entry(const char *name, int role = FWD_OPTION)
 {
-    return FwdEntry{name, C::BX, C::BY, C::NT, &launch_fwd<C>, reinterpret_cast<const void *>(&fwd_kernel<C>)};
+    const void *k;
+    if constexpr (C::OCC > 0)
+        k = reinterpret_cast<const void *>(&fwd_kernel_occ<C>);
+    else
+        k = reinterpret_cast<const void *>(&fwd_kernel<C>);
+    return FwdEntry{name, C::BX, C::BY, C::NT, &launch_fwd<C>, k, role};
 }
 
 template <class C>

@@ -45,7 +45,7 @@ def run_gpu(v, r, h, dt, T, dtype="f32", sources=(), receivers=None, bc="zero", 
                        max_sources=max(1, len(sources) + (1 if ricker else 0)), max_receivers=nrec)
     finally:
         if tuning is not None:
-            F.fd_set_tuning(dtype, r, ndim, 0, 0)
+            F.fd_set_tuning(dtype, r, ndim, -1, 0)  # back to the library's own choice
     if damping is not None:
         p.set_damping(*damping)
     if two_step is not None:

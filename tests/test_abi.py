@@ -100,9 +100,12 @@ def test_layout_sizes(F):
 
 
 def test_tuning_table_accepts_known_configs(F):
-    for cfg in range(8):
+    for cfg in range(9):
         F.fd_set_tuning("f32", 4, 3, cfg)
-    F.fd_set_tuning("f32", 4, 3, 0)  # restore the default
+    F.fd_set_tuning("f32", 4, 3, -1)  # back to the library's own choice
+    with pytest.raises(F.FdError) as e:
+        F.fd_set_tuning("f32", 4, 3, -2)
+    assert e.value.status == F.FD_E_RANGE
     for cfg in range(5):
         F.fd_set_adj_tuning("f32", 4, 3, cfg)
     F.fd_set_adj_tuning("f32", 4, 3, 0)

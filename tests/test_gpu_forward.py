@@ -218,7 +218,7 @@ def test_large_ragged_grid(oracle_mod, shape, r):
 # ----------------------------------------------------------------------------- bitwise invariances
 
 
-@pytest.mark.parametrize("dtype,r,ncfg", [("f32", 4, 8), ("f32", 8, 9), ("f64", 4, 4)])
+@pytest.mark.parametrize("dtype,r,ncfg", [("f32", 4, 9), ("f32", 8, 9), ("f64", 4, 4)])
 def test_tile_shapes_bitwise(oracle_mod, dtype, r, ncfg):
     # the per-point arithmetic does not depend on the tile shape or z chunk, nor on the
     # run: any difference would expose a race or an indexing error
@@ -231,12 +231,29 @@ def test_tile_shapes_bitwise(oracle_mod, dtype, r, ncfg):
     base = run_gpu(v, r, h, dt, T, dtype, receivers=rec, u0=u0, um1=0.5 * u0, ricker=((20, 20, 20), 30.0, 0.0),
                    tuning=(0, 0), label="tile base")
     # (0, 0) again: a repeated run must be bitwise the same (the forward has no atomics)
-    runs = [(0, 0)] + [(c, 0) for c in range(1, ncfg)] + [(0, 5), (0, 8), (0, 41)]
+    # (-1, 0): the library's own choice
+    runs = [(0, 0)] + [(c, 0) for c in range(1, ncfg)] + [(0, 5), (0, 8), (0, 41), (-1, 0)]
     for cfg in runs:
         got = run_gpu(v, r, h, dt, T, dtype, receivers=rec, u0=u0, um1=0.5 * u0, ricker=((20, 20, 20), 30.0, 0.0),
                       tuning=cfg, label=f"tile {cfg}")
         assert np.array_equal(got["u"], base["u"]), (cfg, got["config"])
         assert np.array_equal(got["traces"], base["traces"]), cfg
+
+
+def test_library_tile_choice():
+    # the library's own choice: the 4-waves build of the default tile where the default z
+    # chunks are 16-63 planes (256^3, 320^3), the default tile elsewhere
+    import torch
+
+    from paper_1410_1387_amd import Propagator
+
+    for n, occ in ((64, False), (160, False), (256, True), (320, True), (400, False), (512, False)):
+        v = torch.full((n, n, n), 2000.0, dtype=torch.float32, device="cuda")
+        p = Propagator(v, 4, 10.0, 1e-3, "f32", max_sources=1)
+        cfg = p.kernel_config
+        p.close()
+        say(f"{n}^3: {cfg}")
+        assert ("built for 4 waves/SIMD" in cfg) == occ, (n, cfg)
 
 
 def test_mirror_symmetry_bitwise(oracle_mod):
