@@ -324,12 +324,16 @@ def summarize_prof(d: str, workload: str = DEFAULT_WORKLOAD):
                 out += list(csv.DictReader(fh))
         return out
 
+    first_dispatch = {}
+
     def counter(pattern, name):
         """Counter value per kernel name, per dispatch (in dispatch order)."""
         vals = {}
         for r in rows(pattern):
             if r["Counter_Name"] == name:
                 vals.setdefault(r["Kernel_Name"], []).append((int(r["Dispatch_Id"]), float(r["Counter_Value"])))
+        for k, v in vals.items():
+            first_dispatch[k] = min(first_dispatch.get(k, 1 << 62), min(d for d, _ in v))
         return {k: [x for _, x in sorted(v)] for k, v in vals.items()}
 
     durations = {}
@@ -362,15 +366,21 @@ def summarize_prof(d: str, workload: str = DEFAULT_WORKLOAD):
     shot = forward_shot(workload)
     fwd_json, fwd_sources = FORWARD_WORKLOADS[workload]
     esize = 4 if shot.dtype == "f32" else 8
-    sections = [("fwd_kernel", fwd_json, fwd_sources, 4.0 * esize * int(np.prod(shot.shape)), slice(0, shot.nsteps))]
+    sections = [("fwd_kernel", fwd_json, fwd_sources, 4.0 * esize * int(np.prod(shot.shape)), slice(0, shot.nsteps),
+                 "first")]
     if workload == DEFAULT_WORKLOAD:
-        sections += [("vti_kernel", VTI_PROFILE_TRAFFIC, VTI_KERNEL_SOURCES, 36.0 * 512 ** 3, slice(0, None)),
-                     ("adj_kernel", ADJ_PROFILE_TRAFFIC, ADJ_KERNEL_SOURCES, 28.0 * 256 ** 3, slice(-iso, None))]
-    for tag, out_path, sources, algo, sel in sections:
+        sections += [("vti_kernel", VTI_PROFILE_TRAFFIC, VTI_KERNEL_SOURCES, 36.0 * 512 ** 3, slice(0, None), "most"),
+                     ("adj_kernel", ADJ_PROFILE_TRAFFIC, ADJ_KERNEL_SOURCES, 28.0 * 256 ** 3, slice(-iso, None),
+                      "most")]
+    for tag, out_path, sources, algo, sel, pick in sections:
         cands = [k for k in fetch if tag in k]
         if not cands:
             continue
-        kern = max(cands, key=lambda k: len(fetch[k]))
+        # the forward shot runs first: its kernel is the first forward kernel dispatched
+        # (the gradient section may step its 256^3 grid with another build of the tile);
+        # the other sections take the kernel with the most dispatches
+        kern = (min(cands, key=lambda k: first_dispatch[k]) if pick == "first"
+                else max(cands, key=lambda k: len(fetch[k])))
         avg_ns = mean(durations[kern][sel]) if kern in durations else None
         fb, wb = mean(fetch[kern][sel]) * 1024.0 * f_scale, mean(write[kern][sel]) * 1024.0 * w_scale
         res = {
