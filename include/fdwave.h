@@ -271,7 +271,9 @@ int fd_batch_create(fd_batch **out, int max_shots, void *workspace, size_t ws_by
 int fd_batch_destroy(fd_batch *b);
 
 /* Replace the member set.  Each context advances until its step reaches target[i] (host
- * array); members keep their state and step.  Invalidates the captured graph.  Work still
+ * array); members keep their state and step.  Members must share r, dtype and ndim
+ * (FD_E_INVAL); members whose contexts chose different builds of the stencil tile are
+ * stepped with the default tile (bitwise the same results).  Invalidates the captured graph.  Work still
  * queued on a member's own stream is completed before any batched launch touches it (the
  * batch stream waits for each member stream); the call also waits on the host for earlier
  * batched work, whose shot table it rewrites. */

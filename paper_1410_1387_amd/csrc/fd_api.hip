@@ -1121,18 +1121,35 @@ static int batch_table(fd_ctx *const *ctxs, const int64_t *target, int nctx, con
                        std::vector<ShotDesc> &desc, std::vector<int32_t> &prefix, const FwdEntry **kf_out)
 {
     const FwdEntry *kf = nullptr;
+    bool mixed = false;
     for (int i = 0; i < nctx; ++i) {
         fd_ctx *c = ctxs[i];
         int st = check_ctx(c);
         if (st) return st;
         if (c->bc != FD_BC_ZERO) return fail(FD_E_INVAL, "%s: member %d is not zero-boundary", who, i);
+        if (c->r != ctxs[0]->r || c->dtype != ctxs[0]->dtype || c->g.ndim != ctxs[0]->g.ndim)
+            return fail(FD_E_INVAL, "%s: member %d has another radius, dtype or dimension", who, i);
         if (!kf) kf = c->kf;
-        if (c->kf != kf) return fail(FD_E_INVAL, "%s: member %d uses another kernel (r/dtype/ndim/tile)", who, i);
+        mixed = mixed || c->kf != kf;
         if (target[i] < c->step) return fail(FD_E_INVAL, "%s: target below the member's step", who);
         if (c->nrec > 0 && target[i] - c->rec_base > c->rec_cap)
             return fail(FD_E_RANGE, "%s: member %d target exceeds its trace capacity", who, i);
         for (int j = 0; j < i; ++j)
             if (ctxs[j] == c) return fail(FD_E_INVAL, "%s: member %d appears twice", who, i);
+    }
+    // One launch runs one kernel: members whose contexts chose different tile builds (the
+    // library picks one per grid) are stepped with the default tile, whose tiles fit every
+    // grid; the arithmetic, and so every result, is the same whatever the tile.
+    int slots = nctx > 0 ? ctxs[0]->slots : 0;
+    if (mixed) {
+        int count = 0;
+        kf = &fwd_table(ctxs[0]->dtype, ctxs[0]->r, (int)ctxs[0]->g.ndim, &count)[0];
+        slots = resident_slots(kf->kernel, kf->nt);
+    }
+    std::vector<int64_t> btx((size_t)nctx), bty((size_t)nctx);
+    for (int i = 0; i < nctx; ++i) {
+        btx[(size_t)i] = (ctxs[i]->L.knx + kf->bx - 1) / kf->bx;
+        bty[(size_t)i] = (ctxs[i]->L.kny + kf->by - 1) / kf->by;
     }
     desc.resize((size_t)nctx);
     prefix.assign((size_t)nctx + 1, 0);
@@ -1144,7 +1161,7 @@ static int batch_table(fd_ctx *const *ctxs, const int64_t *target, int nctx, con
     // targets that are some member's exact chunk length.
     std::vector<int64_t> zchm((size_t)nctx, 1);
     if (nctx > 0) {
-        const int r = ctxs[0]->r, slots = ctxs[0]->slots;
+        const int r = ctxs[0]->r;
         std::vector<int64_t> cand;
         for (int i = 0; i < nctx; ++i) {
             const int64_t nz = ctxs[i]->L.knz;
@@ -1158,7 +1175,7 @@ static int batch_table(fd_ctx *const *ctxs, const int64_t *target, int nctx, con
             int64_t nwg = 0, planes = 0;
             for (int i = 0; i < nctx; ++i) {
                 const int64_t nz = ctxs[i]->L.knz, cm = (nz + Z - 1) / Z, zm = (nz + cm - 1) / cm;
-                nwg += ctxs[i]->tiles_x * ctxs[i]->tiles_y * cm;
+                nwg += btx[(size_t)i] * bty[(size_t)i] * cm;
                 planes = std::max<int64_t>(planes, zm);
             }
             const double cost = (double)((nwg + slots - 1) / slots) * (double)(planes + 2 * r);
@@ -1178,10 +1195,12 @@ static int batch_table(fd_ctx *const *ctxs, const int64_t *target, int nctx, con
         d.ctr[0] = c->step;
         d.ctr[1] = c->step;
         d.target = target[i];
+        d.tiles_x = (int32_t)btx[(size_t)i];
+        d.tiles_y = (int32_t)bty[(size_t)i];
         d.zch = (int32_t)zchm[(size_t)i];
         d.chunks_z = (int32_t)((c->L.knz + d.zch - 1) / d.zch);
         desc[(size_t)i] = d;
-        const int64_t next = (int64_t)prefix[(size_t)i] + c->tiles_x * c->tiles_y * d.chunks_z;
+        const int64_t next = (int64_t)prefix[(size_t)i] + btx[(size_t)i] * bty[(size_t)i] * d.chunks_z;
         if (next > INT32_MAX) return fail(FD_E_RANGE, "%s: too many workgroups in one launch", who);
         prefix[(size_t)i + 1] = (int32_t)next;
     }

@@ -88,6 +88,45 @@ def test_batched_graph_replays_match_single(oracle_mod):
     assert rel_l2(refs[1][1], ref["traces"]) <= 1e-4
 
 
+def test_batch_of_members_with_different_tile_builds(oracle_mod):
+    # the library gives a 256^3 grid the 4-waves build of the tile and a small grid the
+    # default one; a batch of both steps them with one kernel, bitwise as each alone
+    import torch
+
+    from paper_1410_1387_amd import fdwave as F
+
+    shots = [_shot((256, 256, 256), 24, 21), _shot((40, 48, 64), 30, 22)]
+    dt = 0.45 * min(oracle_mod.dt_max(3, 4, 10.0, float(s[0].max())) for s in shots)
+    stream = torch.cuda.Stream()
+    ref = []
+    for (v, src, rec, T) in shots:
+        ctx, keep, tr = _make_ctx(v, src, rec, T, dt, stream)
+        F.fd_step(ctx, T)
+        u = torch.empty(v.shape, dtype=torch.float32, device="cuda")
+        F.fd_get_state(ctx, u, None)
+        F.fd_sync(ctx)
+        ref.append((u.cpu().numpy(), tr.cpu().numpy(), F.fd_kernel_config(ctx)))
+        F.fd_destroy(ctx)
+    say(f"tile builds: {ref[0][2]} | {ref[1][2]}")
+    assert ref[0][2].split(", zchunk")[0] != ref[1][2].split(", zchunk")[0]
+    ctxs = [_make_ctx(v, src, rec, T, dt, stream) for (v, src, rec, T) in shots]
+    bws = torch.empty(F.fd_batch_workspace_bytes(2), dtype=torch.uint8, device="cuda")
+    b = F.fd_batch_create(2, bws, F.stream_ptr(stream))
+    F.fd_batch_set(b, [c[0] for c in ctxs], [s[3] for s in shots])
+    F.fd_batch_step(b, 16)
+    F.fd_batch_step(b, 15)
+    for j, ((ctx, keep, tr), (v, *_rest)) in enumerate(zip(ctxs, shots)):
+        u = torch.empty(v.shape, dtype=torch.float32, device="cuda")
+        F.fd_get_state(ctx, u, None)
+        F.fd_sync(ctx)
+        assert F.fd_get_step(ctx) == shots[j][3]
+        assert np.array_equal(u.cpu().numpy(), ref[j][0]), j
+        assert np.array_equal(tr.cpu().numpy(), ref[j][1]), j
+    F.fd_batch_destroy(b)
+    for ctx, keep, tr in ctxs:
+        F.fd_destroy(ctx)
+
+
 def test_batch_orders_member_streams(oracle_mod):
     # Each member on a stream of its own and the batch on another: single steps still
     # queued on a member's stream finish before the batch steps it, and a state read
