@@ -444,7 +444,7 @@ def _oracle_one_thread(workload: str, nsteps: int):
     return json.loads(res.stdout.strip().splitlines()[-1])
 
 
-def run_cpu_baseline(workload: str = DEFAULT_WORKLOAD, budget_s: float = 15.0):
+def run_cpu_baseline(workload: str = DEFAULT_WORKLOAD, budget_s: float = 12.0):
     """The FP64 oracle on the host cores, on a bounded sample of the same workload: the
     full grid and velocity model, a few time steps (throughput per step is constant);
     then the same on one thread (one step), in a child process."""
