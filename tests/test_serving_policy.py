@@ -71,3 +71,33 @@ def test_window_keeps_to_one_kernel():
     assert window(None, [a, b, c, d]) == [a, c]
     a.future.set_result(None)
     assert window(16_000_000, [a, b, c, d]) == [b, d]
+
+
+def test_window_invariants_random():
+    # for any resident set: the oldest live shot always steps; the window holds only shots
+    # of its kernel, in admission order, none finished; it stops at the first shot after
+    # which the fill target is met
+    import random
+
+    rng = random.Random(7)
+    for _ in range(300):
+        shots = []
+        for _k in range(rng.randint(0, 12)):
+            s = live(rng.choice((64, 96, 128, 192, 256, 320)), done=rng.random() < 0.2,
+                     queued_done=rng.random() < 0.1)
+            s.kernel = rng.choice(("k1", "k2"))
+            shots.append(s)
+        fill = rng.choice((None, 1_000_000, 16_000_000, 64_000_000))
+        win = window(fill, shots)
+        livs = [s for s in shots if not s.future.done() and not getattr(s, "_queued_done", False)]
+        if not livs:
+            assert win == []
+            continue
+        assert win[0] is livs[0]
+        assert all(s.kernel == livs[0].kernel for s in win)
+        same = [s for s in livs if s.kernel == livs[0].kernel]
+        assert win == same[: len(win)]
+        if fill is not None:
+            per_step = [s.npoints // s.req.nsteps for s in win]
+            assert sum(per_step[:-1]) < fill           # it did not stop too late
+            assert len(win) == len(same) or sum(per_step) >= fill  # nor too early
