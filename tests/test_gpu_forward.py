@@ -215,6 +215,73 @@ def test_large_ragged_grid(oracle_mod, shape, r):
     _full_grid_case(oracle_mod, shot, 10, 24)
 
 
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_huge_grid_64bit_offsets(oracle_mod, dtype):
+    # A grid of the largest class the layout takes: 1536 x 1536 x 1024 (2.4e9 points; a
+    # padded field is 10 GB in FP32, 20 GB in FP64, so element offsets pass 2^31 and byte
+    # offsets 2^32 part way up the grid).  From a zero start the field after T steps is
+    # zero farther than T*r from every source along each axis, so the oracle run on a box
+    # that reaches r past that support around each source is the exact answer there; one
+    # source sits deep in the grid, one against the far corner (zero ghosts at the last
+    # plane, row and column).  Everywhere outside the boxes the GPU field must be exactly
+    # zero, and receivers there record zeros.
+    import torch
+
+    from paper_1410_1387_amd import Propagator
+
+    nz, ny, nx = 1024, 1536, 1536
+    r, h, T = 4, 10.0, 12
+    reach = T * r + r
+    vz = 1500.0 + 250.0 * (np.arange(nz) // 128)
+    dt = 0.5 * oracle_mod.dt_max(3, r, h, vz.max())
+    rng = np.random.default_rng(41)
+    srcs = [(700, 800, 900), (nx - 3, ny - 2, nz - 2)]
+    wavs = [rng.standard_normal(T) for _ in srcs]
+    boxes = [tuple((max(0, c - reach), min(n, c + reach + 1)) for c, n in ((z, nz), (y, ny), (x, nx)))
+             for x, y, z in srcs]
+    rec = np.array([(705, 790, 903), (696, 812, 880), (nx - 1, ny - 1, nz - 1), (nx - 10, ny - 30, nz - 20),
+                    (3, 3, 3), (700, 800, 100), (1200, 100, 500)], dtype=np.int64)
+
+    def in_box(p, b):
+        return all(lo <= c < hi for c, (lo, hi) in zip((p[2], p[1], p[0]), b))
+
+    tdt = torch.float32 if dtype == "f32" else torch.float64
+    say(f"huge grid {nx}x{ny}x{nz} r={r} T={T} {dtype}")
+    vt = torch.tensor(vz, dtype=tdt, device="cuda").view(nz, 1, 1).expand(nz, ny, nx).contiguous()
+    p = Propagator(vt, r, h, dt, dtype, max_sources=len(srcs), max_receivers=len(rec))
+    del vt
+    for pos, wav in zip(srcs, wavs):
+        p.inject(torch.tensor(wav, dtype=tdt, device="cuda"), pos)
+    tr = p.record(rec, T)
+    p.step(T)
+    u, up, n = p.state()
+    p.sync()
+    cfg = p.kernel_config
+    p.close()
+    del p
+    assert n == T
+    traces = tr.double().cpu().numpy()
+    for (pos, wav), b in zip(zip(srcs, wavs), boxes):
+        (z0, z1), (y0, y1), (x0, x1) = b
+        vb = np.broadcast_to(vz[z0:z1, None, None], (z1 - z0, y1 - y0, x1 - x0)).copy()
+        inside = [j for j in range(len(rec)) if in_box(rec[j], b)]
+        rb = rec[inside] - np.array([x0, y0, z0])
+        ref = oracle_mod.forward(vb, h, dt, r, T, [((pos[0] - x0, pos[1] - y0, pos[2] - z0), wav)], rb)
+        gu = u[z0:z1, y0:y1, x0:x1].double().cpu().numpy()
+        gp = up[z0:z1, y0:y1, x0:x1].double().cpu().numpy()
+        eu, ep = rel_l2(gu, ref["u"]), rel_l2(gp, ref["u_prev"])
+        et = rel_l2(traces[:, inside], ref["traces"])
+        say(f"box around {pos}: rel L2 u {eu:.2e} u_prev {ep:.2e} traces {et:.2e} [{cfg}]")
+        assert eu <= TOL[dtype] and ep <= TOL[dtype] and et <= TOL[dtype]
+        u[z0:z1, y0:y1, x0:x1] = 0
+        up[z0:z1, y0:y1, x0:x1] = 0
+    outside = [j for j in range(len(rec)) if not any(in_box(rec[j], b) for b in boxes)]
+    assert len(outside) == 3 and not traces[:, outside].any()
+    assert int(torch.count_nonzero(u)) == 0 and int(torch.count_nonzero(up)) == 0
+    del u, up, tr
+    torch.cuda.empty_cache()
+
+
 # ----------------------------------------------------------------------------- bitwise invariances
 
 
