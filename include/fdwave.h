@@ -329,6 +329,11 @@ int fd_stream_probe(const void *a, const void *b, void *c, size_t bytes, int blo
  * z-chunk and launch size. */
 const char *fd_kernel_config(const fd_ctx *ctx);
 
+/* The same for the context's adjoint kernel (fd_adjoint_segment): tile shape, z-chunk
+ * and launch size.  The string is owned by the context (valid until fd_destroy); a null
+ * context gives "". */
+const char *fd_adjoint_config(const fd_ctx *ctx);
+
 /* Select a stencil tile configuration by index for contexts created afterwards with this
  * (dtype, r, ndim); returns FD_E_RANGE for an unknown index.  zchunk > 0 overrides the
  * planes each workgroup marches in z.  config = -1 restores the library's own choice,
@@ -339,9 +344,13 @@ const char *fd_kernel_config(const fd_ctx *ctx);
 int fd_set_tuning(fd_dtype dtype, int r, int ndim, int config, int zchunk);
 
 /* The adjoint kernel's tile shape for contexts created afterwards with this (dtype, r,
- * ndim): config indexes the registered adjoint tiles (0 = the default).  Process-wide,
- * thread-safe; a tuning knob like fd_set_tuning.  Errors:
- * FD_E_INVAL (no adjoint kernel for dtype/r/ndim), FD_E_RANGE (config). */
+ * ndim): config indexes the registered adjoint tiles.  config = -1 restores the library's
+ * own choice, which is also what holds before any call: the default tile (index 0, 128
+ * points wide for FP32 radii <= 4), or, for FP32 3-D radii <= 4 on grids whose rows that
+ * tile covers badly (x = 160, 192 or 320, say, where 17-38 % of its lanes would idle), a
+ * 64-point-wide tile (the last registered index).  Process-wide, thread-safe; a tuning
+ * knob like fd_set_tuning; the gradient is bitwise the same whatever the tile.  Errors:
+ * FD_E_INVAL (no adjoint kernel for dtype/r/ndim), FD_E_RANGE (config outside [-1, count)). */
 int fd_set_adj_tuning(fd_dtype dtype, int r, int ndim, int config);
 
 const char *fd_last_error(void);

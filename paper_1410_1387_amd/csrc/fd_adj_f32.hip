@@ -6,14 +6,17 @@
 namespace fdw {
 static const AdjEntry a3_r1[] = {
     adj_entry<TileCfg<float, 1, 3, 32, 16, 1>>("f32 r1 3d tile 128x16 (512 thr, 1 row/thr)"),
+    adj_entry<TileCfg<float, 1, 3, 16, 16, 1>>("f32 r1 3d tile 64x16 (256 thr, 1 row/thr)", ADJ_RAGGED_X),
 };
 static const AdjEntry a2_r1[] = {adj_entry<TileCfg<float, 1, 2, 64, 1, 1>>("f32 r1 2d tile 256x1 (64 thr, 1 row/thr)")};
 static const AdjEntry a3_r2[] = {
     adj_entry<TileCfg<float, 2, 3, 32, 16, 1>>("f32 r2 3d tile 128x16 (512 thr, 1 row/thr)"),
+    adj_entry<TileCfg<float, 2, 3, 16, 16, 1>>("f32 r2 3d tile 64x16 (256 thr, 1 row/thr)", ADJ_RAGGED_X),
 };
 static const AdjEntry a2_r2[] = {adj_entry<TileCfg<float, 2, 2, 64, 1, 1>>("f32 r2 2d tile 256x1 (64 thr, 1 row/thr)")};
 static const AdjEntry a3_r3[] = {
     adj_entry<TileCfg<float, 3, 3, 32, 16, 1>>("f32 r3 3d tile 128x16 (512 thr, 1 row/thr)"),
+    adj_entry<TileCfg<float, 3, 3, 16, 16, 1>>("f32 r3 3d tile 64x16 (256 thr, 1 row/thr)", ADJ_RAGGED_X),
 };
 static const AdjEntry a2_r3[] = {adj_entry<TileCfg<float, 3, 2, 64, 1, 1>>("f32 r3 2d tile 256x1 (64 thr, 1 row/thr)")};
 static const AdjEntry a3_r4[] = {
@@ -22,6 +25,7 @@ static const AdjEntry a3_r4[] = {
     adj_entry<TileCfg<float, 4, 3, 64, 8, 1, 2>>("f32 r4 3d tile 128x8 (512 thr, 1 row/thr, 8-byte vectors)"),
     adj_entry<TileCfg<float, 4, 3, 32, 8, 1, 2>>("f32 r4 3d tile 64x8 (256 thr, 1 row/thr, 8-byte vectors)"),
     adj_entry<TileCfg<float, 4, 3, 16, 16, 1, 2>>("f32 r4 3d tile 32x16 (256 thr, 1 row/thr, 8-byte vectors)"),
+    adj_entry<TileCfg<float, 4, 3, 16, 16, 1>>("f32 r4 3d tile 64x16 (256 thr, 1 row/thr)", ADJ_RAGGED_X),
 };
 static const AdjEntry a2_r4[] = {adj_entry<TileCfg<float, 4, 2, 64, 1, 1>>("f32 r4 2d tile 256x1 (64 thr, 1 row/thr)")};
 static const AdjEntry a3_r5[] = {

@@ -168,6 +168,18 @@ std::map<std::tuple<int, int, int>, int> g_adj_tuning;
 // up to 6 % when batched).
 constexpr int kSmallGridZchMin = 16, kSmallGridZchMax = 64;
 
+// Share of a row's tile lanes that fall past its last point when tiles of width bx cover
+// nx points.  The adjoint takes its ragged-row build where that share is more than
+// kAdjRaggedMargin below the default tile's (measured: 320^3, 192^3 and 160^3 gain 7-17 %
+// with the 64-wide tile; 448^3 is even; 400^3, with 11 points of difference, loses 1 %;
+// grids whose rows are a multiple of 128 lose 4-5 %).
+double row_waste(int64_t nx, int bx)
+{
+    const int64_t cover = (nx + bx - 1) / bx * bx;
+    return 1.0 - (double)nx / (double)cover;
+}
+constexpr double kAdjRaggedMargin = 0.12;
+
 // The last x tile and its halo (at most 8 points) stay inside the padded row, which
 // holds align_up(nx, 256) + 16 points after the interior start: always true of tiles
 // whose width divides 256.
@@ -245,6 +257,7 @@ struct fd_ctx {
     int64_t adj_tiles_x, adj_tiles_y, adj_chunks_z;
     int adj_zch;
     std::string cfg_name;
+    std::string adj_cfg_name;
     // host mirrors
     ShotDesc desc;
     std::vector<SourceRec> sources;
@@ -418,9 +431,9 @@ extern "C" int fd_set_adj_tuning(fd_dtype dtype, int r, int ndim, int config)
     int count = 0;
     const AdjEntry *tab = (dtype == FD_F32 || dtype == FD_F64) ? adj_table(dtype, r, ndim, &count) : nullptr;
     if (!tab || count == 0) return fail(FD_E_INVAL, "fd_set_adj_tuning: bad dtype/r/ndim");
-    if (config < 0 || config >= count) return fail(FD_E_RANGE, "fd_set_adj_tuning: config %d of %d", config, count);
+    if (config < -1 || config >= count) return fail(FD_E_RANGE, "fd_set_adj_tuning: config %d of %d", config, count);
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    if (config == 0)
+    if (config < 0)
         g_adj_tuning.erase(std::make_tuple((int)dtype, r, ndim));
     else
         g_adj_tuning[std::make_tuple((int)dtype, r, ndim)] = config;
@@ -456,7 +469,7 @@ extern "C" int fd_create(fd_ctx **out, const fd_grid *g, int r, double h, double
     if (!tab || count == 0 || !atab || acount == 0) return fail(FD_E_INVAL, "fd_create: no kernel for this dtype/r/ndim");
     Tuning tu{0, 0};
     bool tuned = false;
-    int acfg = 0;
+    int acfg = -1;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tuning.find(std::make_tuple((int)dtype, r, (int)g->ndim));
@@ -466,6 +479,16 @@ extern "C" int fd_create(fd_ctx **out, const fd_grid *g, int r, double h, double
         }
         auto ia = g_adj_tuning.find(std::make_tuple((int)dtype, r, (int)g->ndim));
         if (ia != g_adj_tuning.end()) acfg = ia->second;
+    }
+    if (acfg < 0) {
+        // The library's own adjoint tile: the default, or its ragged-row build (a narrower
+        // tile) where a grid row leaves clearly more of the default tile's lanes idle.
+        acfg = 0;
+        for (int i = 1; i < acount; ++i)
+            if (atab[i].role == ADJ_RAGGED_X) {
+                if (row_waste(L.knx, atab[i].bx) + kAdjRaggedMargin < row_waste(L.knx, atab[0].bx)) acfg = i;
+                break;
+            }
     }
     const AdjEntry *ka = &atab[acfg];
 
@@ -522,6 +545,9 @@ extern "C" int fd_create(fd_ctx **out, const fd_grid *g, int r, double h, double
     snprintf(nm, sizeof(nm), "%s, zchunk %d, grid %lld wg", c->kf->name, c->zch,
              (long long)(c->tiles_x * c->tiles_y * c->chunks_z));
     c->cfg_name = nm;
+    snprintf(nm, sizeof(nm), "%s, zchunk %d, grid %lld wg", c->ka->name, c->adj_zch,
+             (long long)(c->adj_tiles_x * c->adj_tiles_y * c->adj_chunks_z));
+    c->adj_cfg_name = nm;
 
     // zero the workspace: both wavefields (u^0 = u^-1 = 0), c ghosts, tables
     hipError_t e = hipMemsetAsync(workspace, 0, L.total, c->stream);
@@ -591,6 +617,7 @@ extern "C" int fd_set_stream(fd_ctx *ctx, void *stream)
 }
 
 extern "C" const char *fd_kernel_config(const fd_ctx *ctx) { return ctx ? ctx->cfg_name.c_str() : ""; }
+extern "C" const char *fd_adjoint_config(const fd_ctx *ctx) { return ctx ? ctx->adj_cfg_name.c_str() : ""; }
 
 // ------------------------------------------------------------------ sources and receivers
 

@@ -945,11 +945,16 @@ struct FwdEntry {
     int role;
 };
 
+// role of an adjoint table entry: an option for fd_set_adj_tuning, or the build that
+// fd_create takes by itself for grids whose rows the default tile fits badly
+enum { ADJ_OPTION = 0, ADJ_RAGGED_X = 1 };
+
 struct AdjEntry {
     const char *name;
     int bx, by, nt;
     void (*launch)(const AdjArgs &, int nwg, hipStream_t);
     const void *kernel;
+    int role;
 };
 
 template <class C>
@@ -979,9 +984,9 @@ FwdEntry fwd_entry(const char *name, int role = FWD_OPTION)
 }
 
 template <class C>
-AdjEntry adj_entry(const char *name)
+AdjEntry adj_entry(const char *name, int role = ADJ_OPTION)
 {
-    return AdjEntry{name, C::BX, C::BY, C::NT, &launch_adj<C>, reinterpret_cast<const void *>(&adj_kernel<C>)};
+    return AdjEntry{name, C::BX, C::BY, C::NT, &launch_adj<C>, reinterpret_cast<const void *>(&adj_kernel<C>), role};
 }
 
 // Implemented in the per-dtype translation units.

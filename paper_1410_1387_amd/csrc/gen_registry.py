@@ -37,6 +37,11 @@ F64_SWEEP_RADII = {4, 8}
 F2D = (64, 1, 1)          # 2-D forward and adjoint: one row of 64 threads
 # adjoint: radii <= 4 128x16 first (measured 5-7 % faster than 64x16)
 ADJ_F32_3D = [(32, 16, 1), (32, 16, 1, 2), (64, 8, 1, 2), (32, 8, 1, 2), (16, 16, 1, 2)]
+# FP32 3-D adjoint, radii <= 4: a 64-wide tile (256 threads) for grids whose rows leave many
+# of the default 128-wide tile's lanes idle; fd_create takes it by itself there (measured,
+# 205 launches each: 320^3 190.0 vs 203.3 us, 192^3 47.2 vs 53.6, 160^3 32.0 vs 38.5; where
+# 128 divides the row the default is faster: 256^3 92.8 vs 97.0, 512^3 700 vs 733)
+ADJ_F32_RAGGED_X = (16, 16, 1)
 ADJ_F32_3D_BIG_R = [(16, 16, 1), (32, 16, 1, 2)]  # radii > 4: two queues of 2r+2 planes
 ADJ_F64_3D = [(32, 16, 1)]        # radii <= 4: 64x16, 512 threads (256^3: 176.0 vs 189.8 us for 64x8)
 ADJ_F64_3D_BIG_R = [(32, 8, 1)]
@@ -107,9 +112,9 @@ def fwd_file(T, sweep3d, sweep_radii, sweep3d_big_r=None, small_grid=None):
         f.write(out)
 
 
-def adj_file(T, d3, d3_big_r=None):
-    """Adjoint kernels: a list of 3-D tile shapes per radius (the first is the default)
-    and one 2-D shape."""
+def adj_file(T, d3, d3_big_r=None, ragged_x=None):
+    """Adjoint kernels: a list of 3-D tile shapes per radius (the first is the default),
+    the ragged-row build for radii <= 4 (if given), and one 2-D shape."""
     tag = "f32" if T == "float" else "f64"
     out = HDR.format(fname=f"fd_adj_{tag}.hip", what="adjoint", T=T)
     for R in range(1, 9):
@@ -118,6 +123,9 @@ def adj_file(T, d3, d3_big_r=None):
         out += f"static const AdjEntry a3_r{R}[] = {{\n"
         for cfg in lst:
             out += f'    adj_entry<{tilecfg(T, R, 3, *cfg)}>("{cfgname(T, R, 3, *cfg)}"),\n'
+        if ragged_x and R <= 4:
+            out += (f'    adj_entry<{tilecfg(T, R, 3, *ragged_x)}>("{cfgname(T, R, 3, *ragged_x)}", '
+                    f'ADJ_RAGGED_X),\n')
         out += "};\n"
         txn = F2D[0]
         out += (f"static const AdjEntry a2_r{R}[] = {{adj_entry<TileCfg<{T}, {R}, 2, {txn}, 1, 1>>"
@@ -157,7 +165,7 @@ def vti_file(T, tiles):
 if __name__ == "__main__":
     fwd_file("float", F32_3D, F32_SWEEP_RADII, F32_3D_BIG_R, F32_SMALL_GRID)
     fwd_file("double", F64_3D, F64_SWEEP_RADII, F64_3D_BIG_R)
-    adj_file("float", ADJ_F32_3D, ADJ_F32_3D_BIG_R)
+    adj_file("float", ADJ_F32_3D, ADJ_F32_3D_BIG_R, ADJ_F32_RAGGED_X)
     adj_file("double", ADJ_F64_3D, ADJ_F64_3D_BIG_R)
     vti_file("float", VTI_F32)
     vti_file("double", VTI_F64)

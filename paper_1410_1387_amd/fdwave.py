@@ -33,7 +33,7 @@ EXPORTS = [
     "fd_set_stream", "fd_inject", "fd_clear_sources", "fd_set_damping", "fd_record", "fd_ricker", "fd_step", "fd_sync",
     "fd_get_step", "fd_get_state", "fd_set_time_blocking", "fd_set_state", "fd_step_explicit", "fd_adjoint_segment",
     "fd_gradient_finish", "fd_batch_workspace_bytes", "fd_batch_create", "fd_batch_create_noalloc", "fd_batch_destroy",
-    "fd_batch_set", "fd_batch_step", "fd_copy_probe", "fd_stream_probe", "fd_check_finite", "fd_kernel_config", "fd_set_tuning", "fd_set_adj_tuning",
+    "fd_batch_set", "fd_batch_step", "fd_copy_probe", "fd_stream_probe", "fd_check_finite", "fd_kernel_config", "fd_adjoint_config", "fd_set_tuning", "fd_set_adj_tuning",
     "fd_last_error",
     "fd_vti_z_weights", "fd_vti_dt_max", "fd_vti_workspace_bytes", "fd_vti_create", "fd_vti_destroy",
     "fd_vti_inject", "fd_vti_record", "fd_vti_step", "fd_vti_sync", "fd_vti_get_step", "fd_vti_get_state",
@@ -102,6 +102,7 @@ def lib():
             "fd_stream_probe": (ctypes.c_int, [P, P, P, SZ, ctypes.c_int, P]),
             "fd_check_finite": (ctypes.c_int, [P, ctypes.POINTER(ctypes.c_int)]),
             "fd_kernel_config": (ctypes.c_char_p, [P]),
+            "fd_adjoint_config": (ctypes.c_char_p, [P]),
             "fd_set_tuning": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
             "fd_set_adj_tuning": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
             "fd_last_error": (ctypes.c_char_p, []),
@@ -342,6 +343,10 @@ def fd_stream_probe(a, b, c, nbytes: int, blocks: int, stream):
 
 def fd_kernel_config(ctx: int) -> str:
     return lib().fd_kernel_config(ctx).decode()
+
+
+def fd_adjoint_config(ctx: int) -> str:
+    return lib().fd_adjoint_config(ctx).decode()
 
 
 def fd_set_tuning(dtype, r: int, ndim: int, config: int, zchunk: int = 0):

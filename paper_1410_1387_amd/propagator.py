@@ -57,6 +57,11 @@ class Propagator:
     def kernel_config(self) -> str:
         return F.fd_kernel_config(self.ctx)
 
+    @property
+    def adjoint_config(self) -> str:
+        """Tile shape, z-chunk and launch size of this context's adjoint kernel."""
+        return F.fd_adjoint_config(self.ctx)
+
     def close(self):
         if getattr(self, "ctx", None):
             F.fd_destroy(self.ctx)

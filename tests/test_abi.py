@@ -106,12 +106,13 @@ def test_tuning_table_accepts_known_configs(F):
     with pytest.raises(F.FdError) as e:
         F.fd_set_tuning("f32", 4, 3, -2)
     assert e.value.status == F.FD_E_RANGE
-    for cfg in range(5):
+    for cfg in range(6):
         F.fd_set_adj_tuning("f32", 4, 3, cfg)
-    F.fd_set_adj_tuning("f32", 4, 3, 0)
-    with pytest.raises(F.FdError) as e:
-        F.fd_set_adj_tuning("f32", 4, 3, 99)
-    assert e.value.status == F.FD_E_RANGE
+    F.fd_set_adj_tuning("f32", 4, 3, -1)  # back to the library's own choice
+    for bad in (6, -2):
+        with pytest.raises(F.FdError) as e:
+            F.fd_set_adj_tuning("f32", 4, 3, bad)
+        assert e.value.status == F.FD_E_RANGE
     with pytest.raises(F.FdError) as e:
         F.fd_set_adj_tuning("f32", 0, 3, 0)
     assert e.value.status == F.FD_E_INVAL

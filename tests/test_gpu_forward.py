@@ -323,6 +323,27 @@ def test_library_tile_choice():
         assert ("built for 4 waves/SIMD" in cfg) == occ, (n, cfg)
 
 
+def test_library_adjoint_tile_choice():
+    # the adjoint's own choice in FP32: the 64-wide tile where the 128-wide default would
+    # leave clearly more of its lanes past the end of a row (x = 160, 192, 320, 448), the
+    # default where 128 divides the row or the difference is small (x = 400); FP64 has
+    # one tile, 64 wide
+    import torch
+
+    from paper_1410_1387_amd import Propagator
+
+    for nx, ragged in ((128, False), (160, True), (192, True), (256, False), (320, True), (400, False),
+                       (448, True), (512, False)):
+        for dtype in ("f32", "f64"):
+            v = torch.full((24, 40, nx), 2000.0, dtype=torch.float32, device="cuda")
+            p = Propagator(v, 4, 10.0, 1e-3, dtype, max_sources=1)
+            cfg = p.adjoint_config
+            p.close()
+            say(f"x = {nx} {dtype}: adjoint {cfg}")
+            width = 64 if (ragged or dtype == "f64") else 128
+            assert cfg.startswith(f"{dtype} r4 3d tile {width}x16"), (nx, cfg)
+
+
 def test_mirror_symmetry_bitwise(oracle_mod):
     n, r, h, T = 31, 4, 10.0, 90
     v = np.full((n, n, n), 2500.0)
