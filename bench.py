@@ -18,7 +18,8 @@ resident in HBM before the timed region starts.
 
 The JSON line also carries the paper's own benchmark kernel, the two-field VTI
 propagator (R_xy = 12, R_z = 8) on a 512^3 FP32 grid, under "vti"; the 256^3 velocity
-gradient (forward with checkpoints, recompute, adjoint) under "gradient"; and the two
+gradient (every forward state kept in HBM, and from checkpoints with recompute) under
+"gradient"; and the two
 serving traces under "serving", each served three times with continuous batching and
 three times one shot at a time, interleaved, with p50/p99 shot latency of the main
 trace (sides 128-400) on the top level.
@@ -492,10 +493,11 @@ def run_cpu_baseline(workload: str = DEFAULT_WORKLOAD, budget_s: float = 12.0):
 
 def run_gradient():
     """The velocity-gradient workload: 256^3, r = 4, FP32, 2000 steps, true model = layers +
-    3 Gaussian anomalies, start model = layers, 128 x 128 surface receivers, L2 misfit,
-    checkpoints every 50 steps.  Times one FP32 gradient (forward with checkpoints, then
-    the checkpointed adjoint) after a warm-up; observed data from an FP32 forward in the
-    true model."""
+    3 Gaussian anomalies, start model = layers, 128 x 128 surface receivers, L2 misfit.
+    Times one FP32 gradient after a warm-up, twice: keeping every forward state in HBM
+    (when they fit: 2001 padded fields, 178 GB; the adjoint then needs no recompute) and
+    from checkpoints every 50 steps with recomputed segments (bitwise the same gradient);
+    observed data from an FP32 forward in the true model."""
     import torch
 
     import workloads
@@ -516,7 +518,7 @@ def run_gradient():
     obs = obs.clone()
     p.close()
     pb = GradientProblem(r=case.r, h=case.h, dt=dt, nsteps=case.nsteps, source=case.source, receivers=rec,
-                         f0=case.f0, ckpt=case.ckpt, dtype="f32")
+                         f0=case.f0, ckpt=case.ckpt, dtype="f32", states="auto")
     v0t = torch.tensor(v0, dtype=torch.float32, device="cuda")
 
     def once():
@@ -532,23 +534,42 @@ def run_gradient():
         t2 = time.perf_counter()
         return t1 - t0, t2 - t1, float(J.detach()), v.grad
 
+    from paper_1410_1387_amd.autograd import keeps_all_states
+
+    fb = F.fd_field_bytes((case.n,) * 3, case.r, "f32")
     once()
+    kept = keeps_all_states(pb, fb, v0t.device)
     tf, tb, J, g = once()
     n3 = case.n ** 3
     finite = bool(torch.isfinite(g).all().item())
-    log(f"gradient: forward {tf:.3f} s, backward {tb:.3f} s, J {J:.4e}, finite={finite}")
+    log(f"gradient ({'every state kept' if kept else 'checkpoints'}): forward {tf:.3f} s, backward {tb:.3f} s, "
+        f"J {J:.4e}, finite={finite}")
+    del g
+    pb.states = "checkpoint"
+    once()
+    tfc, tbc, Jc, gc = once()
+    log(f"gradient (checkpoints every {case.ckpt} steps): forward {tfc:.3f} s, backward {tbc:.3f} s, "
+        f"J {Jc:.4e}, same misfit: {Jc == J}")
+    del gc
+    torch.cuda.empty_cache()
     adj_ms = time_adjoint_kernel(v0t, case, dt, rec)
     algo = 28.0 * n3
     achieved = algo / (adj_ms * 1e-3) / 1e9
     tr = measured_traffic(ADJ_PROFILE_TRAFFIC, ADJ_KERNEL_SOURCES)
     log(f"adjoint kernel: {adj_ms * 1e3:.1f} us/launch, {achieved:.0f} GB/s algorithmic")
     return {
-        "workload": f"gradient_{case.n}_r{case.r}_fp32_{case.nsteps}steps_ckpt{case.ckpt}",
-        "gradient_s": round(tf + tb, 4), "forward_with_checkpoints_s": round(tf, 4), "backward_s": round(tb, 4),
+        "workload": f"gradient_{case.n}_r{case.r}_fp32_{case.nsteps}steps",
+        "states": ("every forward state kept in HBM (no recompute)" if kept
+                   else f"checkpoints every {case.ckpt} steps (recompute)"),
+        "states_gb": round((case.nsteps + 1) * fb / 1e9, 1) if kept else None,
+        "gradient_s": round(tf + tb, 4), "forward_s": round(tf, 4), "backward_s": round(tb, 4),
         "gpts_per_s": round(n3 * case.nsteps / (tf + tb) / 1e9, 2),
-        "unit": "grid points x time steps per second of a full gradient (forward + recompute + adjoint)",
+        "unit": "grid points x time steps per second of a full gradient (forward + adjoint)",
         "backward_step_us": round(tb / case.nsteps * 1e6, 1), "misfit": J, "finite": finite,
-        "receivers": len(rec), "checkpoints": (case.nsteps + case.ckpt - 1) // case.ckpt,
+        "receivers": len(rec),
+        "checkpointed": {"ckpt": case.ckpt, "gradient_s": round(tfc + tbc, 4), "forward_s": round(tfc, 4),
+                         "backward_s": round(tbc, 4), "backward_step_us": round(tbc / case.nsteps * 1e6, 1),
+                         "same_misfit": Jc == J},
         "adjoint_kernel_roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),

@@ -220,6 +220,13 @@ int fd_set_state(fd_ctx *ctx, const void *u_cur, const void *u_prev, int64_t ste
  * segment into a ring of padded fields for the adjoint. */
 int fd_step_explicit(fd_ctx *ctx, const void *cur, const void *prev, void *out, int64_t step);
 
+/* The same step, recording the receivers registered with fd_record: u^{step+1} at them
+ * goes to row step - (the step at which fd_record was called) of the traces buffer, if
+ * that row lies in [0, cap).  The forward pass of a gradient that keeps every state
+ * (out = a new buffer each step) calls this; fd_adjoint_stored then needs no recompute.
+ * Same arguments and errors as fd_step_explicit. */
+int fd_step_record(fd_ctx *ctx, const void *cur, const void *prev, void *out, int64_t step);
+
 /* ----------------------------------------------------------------- adjoint (gradient) */
 
 /* Discrete adjoint of the forward scheme for J = 1/2 sum_n sum_j resid[n][j]^2 with
@@ -250,6 +257,26 @@ int fd_step_explicit(fd_ctx *ctx, const void *cur, const void *prev, void *out, 
 int fd_adjoint_segment(fd_ctx *ctx, const void *u_ckpt_cur, const void *u_ckpt_prev, int64_t k_lo,
                        int64_t k_hi, void *ring, void *mu, const void *resid, double resid_amp,
                        void *grad, void *grad_seg);
+
+/* The adjoint steps of fd_adjoint_segment (k = k_hi .. k_lo+1, descending, the same
+ * kernel and arithmetic) for a segment whose forward states the caller kept: no
+ * recomputation.  With the states computed by fd_step_record / fd_step_explicit from the
+ * same start the result is bitwise that of fd_adjoint_segment over the same segments.
+ *   states    device, (k_hi - k_lo) consecutive padded fields holding u^{k_lo} ..
+ *             u^{k_hi-1} (field i at byte offset i * fd_field_bytes)
+ *   mu, resid, resid_amp, grad, grad_seg  as for fd_adjoint_segment
+ * Errors: FD_E_INVAL (null states, mu or grad; k_lo < 0; k_hi <= k_lo; no residual with
+ * receivers), FD_E_STATE (periodic or damped context). */
+int fd_adjoint_stored(fd_ctx *ctx, const void *states, int64_t k_lo, int64_t k_hi, void *mu, const void *resid,
+                      double resid_amp, void *grad, void *grad_seg);
+
+/* Zero every cell of `count` consecutive padded fields of this context's layout (field i
+ * at byte offset i * fd_field_bytes) that lies outside the grid's interior: ghost planes,
+ * rows and columns and the alignment padding.  Interiors are left as they are.  A padded
+ * field whose interior the kernels are about to write (a state kept by fd_step_record,
+ * say) needs only this instead of a full clear; a quarter or less of a large field's
+ * bytes.  On the context's stream.  Errors: FD_E_INVAL (null fields, count < 0). */
+int fd_clear_ghosts(fd_ctx *ctx, void *fields, int64_t count);
 
 /* dJ/dv = scale * 2 g / v on the dense grid.
  *   grad_padded  device padded accumulator from fd_adjoint_segment

@@ -902,24 +902,39 @@ extern "C" int fd_set_state(fd_ctx *ctx, const void *u_cur, const void *u_prev, 
     return FD_OK;
 }
 
-extern "C" int fd_step_explicit(fd_ctx *ctx, const void *cur, const void *prev, void *out, int64_t step)
+static int step_explicit(fd_ctx *ctx, const void *cur, const void *prev, void *out, int64_t step, int record,
+                         const char *who)
 {
     int st = check_ctx(ctx);
     if (st) return st;
-    if (!cur || !prev || !out || step < 0) return fail(FD_E_INVAL, "fd_step_explicit: bad arguments");
-    if (out == cur) return fail(FD_E_INVAL, "fd_step_explicit: out must not alias cur");
-    if (ctx->bc != FD_BC_ZERO) return fail(FD_E_STATE, "fd_step_explicit: zero boundary only");
+    if (!cur || !prev || !out || step < 0) return fail(FD_E_INVAL, "%s: bad arguments", who);
+    if (out == cur) return fail(FD_E_INVAL, "%s: out must not alias cur", who);
+    if (ctx->bc != FD_BC_ZERO) return fail(FD_E_STATE, "%s: zero boundary only", who);
     LaunchArgs a = direct_args(ctx, step);
     a.cur = cur;
     a.prev = prev;
     a.out = out;
-    a.record = 0;
+    a.record = record;
     ctx->kf->launch(a, (int)nwg_of(ctx), ctx->stream);
     HIP_TRY(ctx, hipGetLastError());
     return FD_OK;
 }
 
+extern "C" int fd_step_explicit(fd_ctx *ctx, const void *cur, const void *prev, void *out, int64_t step)
+{
+    return step_explicit(ctx, cur, prev, out, step, 0, "fd_step_explicit");
+}
+
+extern "C" int fd_step_record(fd_ctx *ctx, const void *cur, const void *prev, void *out, int64_t step)
+{
+    return step_explicit(ctx, cur, prev, out, step, 1, "fd_step_record");
+}
+
 // ------------------------------------------------------------------ adjoint
+
+template <class Slot>
+static int adjoint_steps(fd_ctx *ctx, const Slot &slot, int64_t k_lo, int64_t k_hi, void *mu, const void *resid,
+                         double resid_amp, void *grad, void *grad_seg);
 
 extern "C" int fd_adjoint_segment(fd_ctx *ctx, const void *u_ckpt_cur, const void *u_ckpt_prev, int64_t k_lo,
                                   int64_t k_hi, void *ring, void *mu, const void *resid, double resid_amp, void *grad,
@@ -943,7 +958,33 @@ extern "C" int fd_adjoint_segment(fd_ctx *ctx, const void *u_ckpt_cur, const voi
         int s2 = fd_step_explicit(ctx, slot(i - 1), prev, slot(i), k_lo + i - 1);
         if (s2) return s2;
     }
-    // adjoint steps k = k_hi .. k_lo + 1
+    return adjoint_steps(ctx, slot, k_lo, k_hi, mu, resid, resid_amp, grad, grad_seg);
+}
+
+extern "C" int fd_adjoint_stored(fd_ctx *ctx, const void *states, int64_t k_lo, int64_t k_hi, void *mu,
+                                 const void *resid, double resid_amp, void *grad, void *grad_seg)
+{
+    int st = check_ctx(ctx);
+    if (st) return st;
+    if (ctx->bc != FD_BC_ZERO) return fail(FD_E_STATE, "fd_adjoint_stored: zero boundary only");
+    if (ctx->desc.damp) return fail(FD_E_STATE, "fd_adjoint_stored: the adjoint of the damped scheme is not built");
+    if (k_lo < 0 || k_hi - k_lo < 1 || !states || !mu || !grad)
+        return fail(FD_E_INVAL, "fd_adjoint_stored: bad arguments");
+    if (ctx->nrec > 0 && !resid) return fail(FD_E_INVAL, "fd_adjoint_stored: null residual");
+    const size_t fb = ctx->L.field_bytes;
+    auto slot = [&](int64_t i) -> void * {  // u^{k_lo + i}
+        return const_cast<char *>(static_cast<const char *>(states)) + (size_t)i * fb;
+    };
+    return adjoint_steps(ctx, slot, k_lo, k_hi, mu, resid, resid_amp, grad, grad_seg);
+}
+
+// Adjoint steps k = k_hi .. k_lo + 1, u^{k-1} taken from slot(k - 1 - k_lo).
+template <class Slot>
+static int adjoint_steps(fd_ctx *ctx, const Slot &slot, int64_t k_lo, int64_t k_hi, void *mu, const void *resid,
+                         double resid_amp, void *grad, void *grad_seg)
+{
+    const size_t fb = ctx->L.field_bytes;
+    const int64_t nk = k_hi - k_lo;
     void *m[2] = {mu, (char *)mu + fb};
     const int64_t nwg = ctx->adj_tiles_x * ctx->adj_tiles_y * ctx->adj_chunks_z;
     for (int64_t k = k_hi; k > k_lo; --k) {
@@ -970,6 +1011,29 @@ extern "C" int fd_adjoint_segment(fd_ctx *ctx, const void *u_ckpt_cur, const voi
         ctx->ka->launch(a, (int)nwg, ctx->stream);
         HIP_TRY(ctx, hipGetLastError());
     }
+    return FD_OK;
+}
+
+extern "C" int fd_clear_ghosts(fd_ctx *ctx, void *fields, int64_t count)
+{
+    int st = check_ctx(ctx);
+    if (st) return st;
+    if (!fields || count < 0) return fail(FD_E_INVAL, "fd_clear_ghosts: bad arguments");
+    if (count == 0) return FD_OK;
+    const Layout &L = ctx->L;
+    GhostBox b;
+    b.count = count;
+    b.field_elems = (int64_t)(L.field_bytes / (size_t)L.esize);
+    b.px = L.px;
+    b.py = L.py;
+    b.planes = L.planes;
+    b.y0 = L.ndim == 3 ? L.r : 0;
+    b.z0 = L.r;
+    b.x0 = L.off0 - b.z0 * L.pxy - b.y0 * L.px;
+    b.nx = L.knx;
+    b.ny = L.kny;
+    b.nz = L.knz;
+    HIP_TRY(ctx, launch_clear_ghosts((int)ctx->dtype, b, fields, ctx->stream));
     return FD_OK;
 }
 

@@ -18,6 +18,15 @@ constexpr int kPrepBlocks = 1024;  // partial min/max slots the prep kernel writ
 hipError_t launch_prep(int dtype, const Geom &g, const void *v, void *c, double k, double *partial,
                        double *minmax, hipStream_t st);
 hipError_t launch_pack(int dtype, const Geom &g, const void *padded, void *dense, hipStream_t st);
+
+// count consecutive padded fields of field_elems elements each: rows of px elements,
+// py rows per plane, `planes` planes; the interior is x in [x0, x0 + nx), y in
+// [y0, y0 + ny), plane in [z0, z0 + nz)
+struct GhostBox {
+    int64_t count, field_elems, px, py, planes;
+    int64_t x0, y0, z0, nx, ny, nz;
+};
+hipError_t launch_clear_ghosts(int dtype, const GhostBox &b, void *fields, hipStream_t st);
 hipError_t launch_unpack(int dtype, const Geom &g, const void *dense, void *padded, hipStream_t st);
 hipError_t launch_halo_periodic(int dtype, const Geom &g, int hx, int hy, int hz, void *u, hipStream_t st);
 hipError_t launch_ricker(int dtype, void *out, int64_t nsamp, double dt, double f0, double t0, hipStream_t st);

@@ -297,6 +297,40 @@ hipError_t launch_pack(int dtype, const Geom &g, const void *padded, void *dense
     return hipGetLastError();
 }
 
+// Zero what lies outside the interior of each field: one wave per row (grid-stride
+// over rows); rows outside the interior's planes and rows are cleared whole, interior
+// rows only left and right of [x0, x0 + nx).
+template <typename T>
+__global__ void clear_ghosts_kernel(GhostBox b, T *__restrict__ f)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const int64_t rows_per_field = b.planes * b.py;
+    const int64_t rows = b.count * rows_per_field;
+    for (int64_t row = wave; row < rows; row += nwaves) {
+        const int64_t fi = row / rows_per_field, rf = row % rows_per_field;
+        const int64_t z = rf / b.py, y = rf % b.py;
+        T *p = f + fi * b.field_elems + rf * b.px;
+        if (z < b.z0 || z >= b.z0 + b.nz || y < b.y0 || y >= b.y0 + b.ny) {
+            for (int64_t x = lane; x < b.px; x += 64) p[x] = T(0);
+        } else {
+            for (int64_t x = lane; x < b.x0; x += 64) p[x] = T(0);
+            for (int64_t x = b.x0 + b.nx + lane; x < b.px; x += 64) p[x] = T(0);
+        }
+    }
+}
+
+hipError_t launch_clear_ghosts(int dtype, const GhostBox &b, void *fields, hipStream_t st)
+{
+    const int nb = blocks_for(b.count * b.planes * b.py * 64);
+    if (dtype == 0)
+        hipLaunchKernelGGL(clear_ghosts_kernel<float>, dim3(nb), dim3(kThreads), 0, st, b, (float *)fields);
+    else
+        hipLaunchKernelGGL(clear_ghosts_kernel<double>, dim3(nb), dim3(kThreads), 0, st, b, (double *)fields);
+    return hipGetLastError();
+}
+
 hipError_t launch_unpack(int dtype, const Geom &g, const void *dense, void *padded, hipStream_t st)
 {
     const int nb = blocks_for((int64_t)g.nx * g.ny * g.nz);

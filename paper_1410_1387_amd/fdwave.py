@@ -31,9 +31,10 @@ STATUS_NAMES = {
 EXPORTS = [
     "fd_weights", "fd_dt_max", "fd_field_bytes", "fd_workspace_bytes", "fd_create", "fd_destroy",
     "fd_set_stream", "fd_inject", "fd_clear_sources", "fd_set_damping", "fd_record", "fd_ricker", "fd_step", "fd_sync",
-    "fd_get_step", "fd_get_state", "fd_set_time_blocking", "fd_set_state", "fd_step_explicit", "fd_adjoint_segment",
-    "fd_gradient_finish", "fd_batch_workspace_bytes", "fd_batch_create", "fd_batch_create_noalloc", "fd_batch_destroy",
-    "fd_batch_set", "fd_batch_step", "fd_copy_probe", "fd_stream_probe", "fd_check_finite", "fd_kernel_config", "fd_adjoint_config", "fd_set_tuning", "fd_set_adj_tuning",
+    "fd_get_step", "fd_get_state", "fd_set_time_blocking", "fd_set_state", "fd_step_explicit", "fd_step_record",
+    "fd_adjoint_segment", "fd_adjoint_stored", "fd_clear_ghosts", "fd_gradient_finish", "fd_batch_workspace_bytes", "fd_batch_create",
+    "fd_batch_create_noalloc", "fd_batch_destroy", "fd_batch_set", "fd_batch_step", "fd_copy_probe", "fd_stream_probe",
+    "fd_check_finite", "fd_kernel_config", "fd_adjoint_config", "fd_set_tuning", "fd_set_adj_tuning",
     "fd_last_error",
     "fd_vti_z_weights", "fd_vti_dt_max", "fd_vti_workspace_bytes", "fd_vti_create", "fd_vti_destroy",
     "fd_vti_inject", "fd_vti_record", "fd_vti_step", "fd_vti_sync", "fd_vti_get_step", "fd_vti_get_state",
@@ -90,7 +91,10 @@ def lib():
             "fd_get_state": (ctypes.c_int, [P, P, P, ctypes.POINTER(I64), ctypes.c_int]),
             "fd_set_state": (ctypes.c_int, [P, P, P, I64, ctypes.c_int]),
             "fd_step_explicit": (ctypes.c_int, [P, P, P, P, I64]),
+            "fd_step_record": (ctypes.c_int, [P, P, P, P, I64]),
             "fd_adjoint_segment": (ctypes.c_int, [P, P, P, I64, I64, P, P, P, D, P, P]),
+            "fd_adjoint_stored": (ctypes.c_int, [P, P, I64, I64, P, P, D, P, P]),
+            "fd_clear_ghosts": (ctypes.c_int, [P, P, I64]),
             "fd_gradient_finish": (ctypes.c_int, [P, P, P, P, D]),
             "fd_batch_workspace_bytes": (SZ, [ctypes.c_int]),
             "fd_batch_create": (ctypes.c_int, [ctypes.POINTER(P), ctypes.c_int, P, SZ, P]),
@@ -284,10 +288,23 @@ def fd_step_explicit(ctx: int, cur, prev, out, step: int):
     _check(lib().fd_step_explicit(ctx, ptr(cur), ptr(prev), ptr(out), int(step)), "fd_step_explicit")
 
 
+def fd_step_record(ctx: int, cur, prev, out, step: int):
+    _check(lib().fd_step_record(ctx, ptr(cur), ptr(prev), ptr(out), int(step)), "fd_step_record")
+
+
 def fd_adjoint_segment(ctx: int, ckpt_cur, ckpt_prev, k_lo: int, k_hi: int, ring, mu, resid, resid_amp: float, grad,
                        grad_seg=None):
     _check(lib().fd_adjoint_segment(ctx, ptr(ckpt_cur), ptr(ckpt_prev), int(k_lo), int(k_hi), ptr(ring), ptr(mu),
                                     ptr(resid), float(resid_amp), ptr(grad), ptr(grad_seg)), "fd_adjoint_segment")
+
+
+def fd_adjoint_stored(ctx: int, states, k_lo: int, k_hi: int, mu, resid, resid_amp: float, grad, grad_seg=None):
+    _check(lib().fd_adjoint_stored(ctx, ptr(states), int(k_lo), int(k_hi), ptr(mu), ptr(resid), float(resid_amp),
+                                   ptr(grad), ptr(grad_seg)), "fd_adjoint_stored")
+
+
+def fd_clear_ghosts(ctx: int, fields, count: int):
+    _check(lib().fd_clear_ghosts(ctx, ptr(fields), int(count)), "fd_clear_ghosts")
 
 
 def fd_gradient_finish(ctx: int, grad_padded, velocity, out, scale: float):

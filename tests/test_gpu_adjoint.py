@@ -69,6 +69,7 @@ def test_checkpoint_interval_bitwise(oracle_mod):
     # recomputing a segment repeats the forward arithmetic exactly, so the gradient cannot
     # depend on where the checkpoints are
     v, pb, obs = _problem(oracle_mod, (17, 22, 26), 4, 60, 1, "f32", seed=7)
+    pb.states = "checkpoint"
     grads = []
     for K in (1, 7, 60, 100):
         pb.ckpt = K
@@ -76,6 +77,36 @@ def test_checkpoint_interval_bitwise(oracle_mod):
         grads.append(_gpu_gradient(v, pb, obs)[1])
     for gk in grads[1:]:
         assert np.array_equal(gk, grads[0])
+
+
+@pytest.mark.parametrize("shape,r,T", [((17, 22, 26), 4, 60), ((19, 23, 21), 8, 45), ((40, 52), 3, 70)])
+def test_kept_states_bitwise_checkpointed(oracle_mod, shape, r, T):
+    # keeping every forward state (fd_step_record + fd_adjoint_stored) and recomputing
+    # checkpoint segments (fd_adjoint_segment) hand the adjoint the same states, so the
+    # gradients agree bit for bit, with and without per-segment blocking of the sum
+    from paper_1410_1387_amd.autograd import WaveProp
+
+    v, pb, obs = _problem(oracle_mod, shape, r, T, 1, "f32", seed=13)
+    for blocked in (False, True):
+        for K in (1, 7, T):
+            pb.ckpt, pb.blocked = K, blocked
+            got = {}
+            for mode in ("all", "checkpoint"):
+                pb.states = mode
+                say(f"{shape} r={r}: states {mode}, K={K}, blocked={blocked}")
+                got[mode] = _gpu_gradient(v, pb, obs)[1]
+            assert np.linalg.norm(got["all"]) > 0
+            assert np.array_equal(got["all"], got["checkpoint"]), (K, blocked)
+    # the traces of the kept-states forward pass are those of a plain shot, bit for bit
+    import torch
+
+    tdt = torch.float32
+    vt = torch.tensor(v, dtype=tdt, device="cuda")
+    pb.states = "all"
+    tr_all = WaveProp.apply(vt, pb).detach()
+    pb.states = "checkpoint"
+    tr_ck = WaveProp.apply(vt, pb).detach()
+    assert torch.equal(tr_all, tr_ck)
 
 
 @pytest.mark.parametrize("r,ncfg", [(4, 6), (8, 2)])

@@ -636,6 +636,35 @@ def test_two_step_full_grid_bitwise(oracle_mod):
         assert np.array_equal(a[f], b[f]), f
 
 
+@pytest.mark.parametrize("dtype,shape", [("f32", (23, 37, 70)), ("f64", (9, 130, 65)), ("f32", (57, 301))])
+def test_clear_ghosts(dtype, shape):
+    # fd_clear_ghosts zeroes exactly the cells outside the interior of each field: fields
+    # filled with a marker keep it at every interior point (read back through
+    # fd_get_state's padded-to-dense unpacking) and hold nothing else
+    import torch
+
+    from paper_1410_1387_amd import Propagator
+    from paper_1410_1387_amd import fdwave as F
+
+    tdt = torch.float32 if dtype == "f32" else torch.float64
+    p = Propagator(torch.full(shape, 1500.0, dtype=tdt, device="cuda"), 4, 10.0, 1e-3, dtype, max_sources=1)
+    n = p.field_bytes // torch.tensor([], dtype=tdt).element_size()
+    fields = torch.full((3, n), 7.0, dtype=tdt, device="cuda")
+    fields[1] = 5.0
+    say(f"fd_clear_ghosts {dtype} {shape}: {n} elements per field")
+    F.fd_clear_ghosts(p.ctx, fields[1], 2)
+    p.sync()
+    assert bool((fields[0] == 7.0).all())  # outside the range: untouched
+    npts = int(np.prod(shape))
+    for k, val in ((1, 5.0), (2, 7.0)):
+        assert int(torch.count_nonzero(fields[k])) == npts
+        assert float(fields[k].sum()) == val * npts
+        F.fd_set_state(p.ctx, fields[k], fields[k], 3, F.FD_PADDED)
+        u, up, _ = p.state()
+        assert bool((u == val).all()) and bool((up == val).all())
+    p.close()
+
+
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
 def test_check_finite_probe(oracle_mod, dtype):
     # the failure-detection probe: true on a clean run (and it leaves the run bitwise as

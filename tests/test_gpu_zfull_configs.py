@@ -117,11 +117,18 @@ def test_c4_gradient_vs_oracle(oracle_mod, progress):
                               progress=progress)
     g_ref = ref["grad_v"]
     pb = GradientProblem(r=case.r, h=case.h, dt=dt, nsteps=T, source=case.source, receivers=rec, f0=case.f0,
-                         ckpt=case.ckpt, dtype="f32")
-    progress("GPU FP32 gradient end to end (observed data from the oracle)")
+                         ckpt=case.ckpt, dtype="f32", states="all")
+    progress("GPU FP32 gradient end to end (observed data from the oracle), every forward state kept")
     J32, g32 = gradient(torch.tensor(v0, dtype=torch.float32, device="cuda"), pb,
                         torch.tensor(obs, dtype=torch.float64, device="cuda"))
     e_e2e = rel_l2(g32.double().cpu().numpy(), g_ref)
+    progress("the same gradient from checkpoints every 50 steps and recomputed segments")
+    pb.states = "checkpoint"
+    J32c, g32c = gradient(torch.tensor(v0, dtype=torch.float32, device="cuda"), pb,
+                          torch.tensor(obs, dtype=torch.float64, device="cuda"))
+    assert J32c == J32 and torch.equal(g32c, g32)
+    del g32c
+    torch.cuda.empty_cache()
     progress("GPU FP32 adjoint applied to the oracle's FP64 residual")
     resid = torch.tensor(ref["traces"] - obs, dtype=torch.float32, device="cuda")
     v32 = torch.tensor(v0, dtype=torch.float32, device="cuda").requires_grad_(True)
