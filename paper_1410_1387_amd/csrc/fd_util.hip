@@ -1,10 +1,13 @@
 // fd_util.hip -- element-wise device kernels around the stencil: model preparation
 // (v -> c = (v dt / h)^2 in the padded layout, with min/max of v), dense <-> padded
-// copies, the periodic ghost fill, Ricker samples, the gradient finish and the
-// bandwidth probe.  All are HBM-bound streaming kernels with grid-stride loops.
+// copies, the periodic ghost fill, clearing of ghost cells, Ricker samples, the gradient
+// finish and the bandwidth probe.  All are HBM-bound streaming kernels with grid-stride
+// loops.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
+
+#include <algorithm>
 
 #include "fd_util.h"
 
@@ -297,33 +300,40 @@ hipError_t launch_pack(int dtype, const Geom &g, const void *padded, void *dense
     return hipGetLastError();
 }
 
-// Zero what lies outside the interior of each field: one wave per row (grid-stride
-// over rows); rows outside the interior's planes and rows are cleared whole, interior
-// rows only left and right of [x0, x0 + nx).
+// Zero what lies outside the interior of each field, one plane per workgroup at a time
+// (grid-stride over planes): planes outside the interior's z range are cleared whole,
+// and so are the rows above and below the interior's y range (contiguous runs);
+// each interior row is cleared left and right of [x0, x0 + nx) by one wave, its lanes
+// taking the row's pad elements in turn.
 template <typename T>
 __global__ void clear_ghosts_kernel(GhostBox b, T *__restrict__ f)
 {
-    const int lane = threadIdx.x & 63;
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    const int64_t rows_per_field = b.planes * b.py;
-    const int64_t rows = b.count * rows_per_field;
-    for (int64_t row = wave; row < rows; row += nwaves) {
-        const int64_t fi = row / rows_per_field, rf = row % rows_per_field;
-        const int64_t z = rf / b.py, y = rf % b.py;
-        T *p = f + fi * b.field_elems + rf * b.px;
-        if (z < b.z0 || z >= b.z0 + b.nz || y < b.y0 || y >= b.y0 + b.ny) {
-            for (int64_t x = lane; x < b.px; x += 64) p[x] = T(0);
-        } else {
-            for (int64_t x = lane; x < b.x0; x += 64) p[x] = T(0);
-            for (int64_t x = b.x0 + b.nx + lane; x < b.px; x += 64) p[x] = T(0);
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int wave = tid >> 6, lane = tid & 63, nw = nt >> 6;
+    const int64_t plane_elems = b.py * b.px;
+    const int x0 = (int)b.x0, nx = (int)b.nx, y0 = (int)b.y0, ny = (int)b.ny;
+    const int padw = (int)(b.px - b.nx);  // pad elements per interior row
+    for (int64_t pl = blockIdx.x; pl < b.count * b.planes; pl += gridDim.x) {
+        const int64_t fi = pl / b.planes;
+        const int64_t z = pl - fi * b.planes;
+        T *P = f + fi * b.field_elems + z * plane_elems;
+        if (z < b.z0 || z >= b.z0 + b.nz) {
+            for (int64_t e = tid; e < plane_elems; e += nt) P[e] = T(0);
+            continue;
+        }
+        for (int64_t e = tid; e < (int64_t)y0 * b.px; e += nt) P[e] = T(0);
+        for (int64_t e = (int64_t)(y0 + ny) * b.px + tid; e < plane_elems; e += nt) P[e] = T(0);
+        for (int y = y0 + wave; y < y0 + ny; y += nw) {
+            T *row = P + (int64_t)y * b.px;
+            for (int k = lane; k < padw; k += 64) row[k < x0 ? k : k + nx] = T(0);
         }
     }
 }
 
 hipError_t launch_clear_ghosts(int dtype, const GhostBox &b, void *fields, hipStream_t st)
 {
-    const int nb = blocks_for(b.count * b.planes * b.py * 64);
+    const int64_t planes = b.count * b.planes;
+    const int nb = (int)std::min<int64_t>(planes, 16384);
     if (dtype == 0)
         hipLaunchKernelGGL(clear_ghosts_kernel<float>, dim3(nb), dim3(kThreads), 0, st, b, (float *)fields);
     else
