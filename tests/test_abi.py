@@ -83,6 +83,24 @@ def test_invalid_arguments_rejected(F):
     assert F.fd_batch_workspace_bytes(0) == 0
 
 
+def test_null_context_rejected(F):
+    # entry points that take a context refuse a null one with FD_E_INVAL before touching
+    # any device; the configuration queries give an empty string
+    calls = [
+        lambda: F.fd_step_explicit(None, None, None, None, 0),
+        lambda: F.fd_step_record(None, None, None, None, 0),
+        lambda: F.fd_adjoint_segment(None, None, None, 0, 1, None, None, None, 1.0, None),
+        lambda: F.fd_adjoint_stored(None, None, 0, 1, None, None, 1.0, None),
+        lambda: F.fd_clear_ghosts(None, None, 1),
+        lambda: F.fd_gradient_finish(None, None, None, None, 1.0),
+    ]
+    for call in calls:
+        with pytest.raises(F.FdError) as e:
+            call()
+        assert e.value.status == F.FD_E_INVAL
+    assert F.fd_kernel_config(None) == "" and F.fd_adjoint_config(None) == ""
+
+
 def test_layout_sizes(F):
     # padded field: interior plus r ghost cells on every face plus alignment padding
     for shape, r, dt, es in [((512, 512, 512), 4, "f32", 4), ((384, 384, 384), 8, "f32", 4),
