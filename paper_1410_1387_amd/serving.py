@@ -68,6 +68,8 @@ class ShotRequest:
     shape: Optional[tuple] = None  # grid shape; required when velocity is a callable
 
     def grid_shape(self) -> tuple:
+        if int(self.nsteps) < 0:
+            raise ValueError(f"nsteps must be >= 0, not {self.nsteps}")
         if self.shape is not None:
             return tuple(self.shape)
         if callable(self.velocity):
@@ -148,9 +150,10 @@ class _ShotFactory:
                                                                              float(v.max()))
         ctx = F.fd_create(shape, self.r, req.h, dt, v, self.dtype, "zero", ws, 1, nrec, sp)
         try:
-            F.fd_ricker(wav, dt, req.f0, 1.5 / req.f0 if req.t0 is None else req.t0, sp)
-            F.fd_inject(ctx, wav, req.source, 1.0)
-            F.fd_record(ctx, req.receivers, traces, req.nsteps)
+            if req.nsteps > 0:  # a shot of zero steps has no samples and records nothing
+                F.fd_ricker(wav, dt, req.f0, 1.5 / req.f0 if req.t0 is None else req.t0, sp)
+                F.fd_inject(ctx, wav, req.source, 1.0)
+                F.fd_record(ctx, req.receivers, traces, req.nsteps)
             F.fd_sync(ctx)
         except Exception:
             F.fd_destroy(ctx)
@@ -438,6 +441,7 @@ def run_sequential(requests: list, r: int = 4, dtype: str = "f32", realtime: boo
         arrival = req.arrival if realtime else now()
         start = now()
         try:
+            req.grid_shape()  # validates the request
             ctx, tensors, traces, fp, npts = factory.create(req, stream)
         except Exception as e:
             msg = str(e) if isinstance(e, F.FdError) else f"{type(e).__name__}: {e}"

@@ -275,6 +275,33 @@ def test_server_isolates_bad_requests():
     assert seq[93].status == "failed" and all(seq[i].status == "ok" for i in range(4))
 
 
+def test_server_zero_and_negative_steps():
+    # a shot of zero steps is served at once with an empty trace set (nothing to inject or
+    # record) and leaves the others bitwise unchanged; a negative step count fails alone
+    import dataclasses
+
+    from paper_1410_1387_amd.serving import ShotServer, run_sequential
+
+    reqs = _requests(3, 11, spread=0.0)
+    zero = dataclasses.replace(reqs[0], rid=80, nsteps=0)
+    neg = dataclasses.replace(reqs[1], rid=81, nsteps=-5)
+    ref = {r.rid: r for r in run_sequential(reqs, realtime=False)}
+    for name, res in (("batched", ShotServer(r=4, chunk=8, max_shots=8).serve_trace(reqs + [zero, neg], realtime=False)),
+                      ("one at a time", run_sequential(reqs + [zero, neg], realtime=False))):
+        res = {r.rid: r for r in res}
+        say(f"{name}: zero-step {res[80].status}, negative {res[81].status} ({res[81].error})")
+        assert res[80].status == "ok" and tuple(res[80].traces.shape) == (0, len(zero.receivers))
+        assert res[81].status == "failed" and "nsteps" in res[81].error
+        for i in range(3):
+            assert res[i].status == "ok" and torch_equal(res[i].traces, ref[i].traces)
+
+
+def torch_equal(a, b):
+    import torch
+
+    return bool(torch.equal(a, b))
+
+
 def test_server_real_sizes_alone_vs_mix_bitwise(oracle_mod):
     # the serving workload's own requests (sides 128-400, layered models built on the GPU,
     # surface receivers), with their step counts cut to 37-96 so the test stays short:
