@@ -252,6 +252,76 @@ def test_vti_full_grid_sampled(oracle_mod):
         say(f"  sample {(sx, sy, sz)} ok")
 
 
+def test_vti_huge_grid_64bit_offsets(oracle_mod):
+    """1536 x 1536 x 1024 FP32 (2.4e9 points, seven padded fields of 10 GB: element offsets
+    past 2^31, byte offsets past 2^32), R_xy = 4, R_z = 2, a model layered in z.  From a zero
+    start the fields after T steps are zero farther than T R_xy (x, y) or T R_z (z) from
+    each source, so the oracle run on a box around each source reaching one stencil radius
+    past that support is the exact answer there; one source sits deep in the grid, one
+    against the far corner.  Outside the boxes every field must be exactly zero."""
+    import torch
+
+    from paper_1410_1387_amd.vti import VtiPropagator
+
+    nz, ny, nx = 1024, 1536, 1536
+    rxy, rz, h, T = 4, 2, 10.0, 10
+    kz = np.arange(nz) // 128
+    vz_z = 1800.0 + 200.0 * kz
+    eps_z = 0.05 + 0.02 * kz
+    delta_z = 0.5 * eps_z
+    zc = oracle_mod.uniform_z(nz, rz, h)
+    dt = 0.5 * VtiPropagator.dt_max(rxy, rz, h, nz, float(vz_z.max()), float(eps_z.max()), float(delta_z.max()))
+    rng = np.random.default_rng(43)
+    srcs = [((700, 800, 900), 1.0, 0.0), ((nx - 3, ny - 2, nz - 2), 1.0, 0.6)]
+    wavs = [rng.standard_normal(T) for _ in srcs]
+    rxh, rzh = T * rxy + rxy, T * rz + rz
+    boxes = [((max(0, z - rzh), min(nz, z + rzh + 1)), (max(0, y - rxh), min(ny, y + rxh + 1)),
+              (max(0, x - rxh), min(nx, x + rxh + 1))) for (x, y, z), _, _ in srcs]
+    rec = np.array([(705, 790, 903), (nx - 1, ny - 1, nz - 1), (nx - 10, ny - 30, nz - 15), (5, 5, 5),
+                    (700, 800, 100)], dtype=np.int64)
+
+    def in_box(pos, b):
+        return all(lo <= c < hi for c, (lo, hi) in zip((pos[2], pos[1], pos[0]), b))
+
+    say(f"huge VTI grid {nx}x{ny}x{nz} rxy={rxy} rz={rz} T={T}")
+    col = lambda a: torch.tensor(a, dtype=torch.float32, device="cuda").view(nz, 1, 1).expand(nz, ny, nx).contiguous()
+    vz_t, eps_t, delta_t = col(vz_z), col(eps_z), col(delta_z)
+    p = VtiPropagator(vz_t, eps_t, delta_t, rxy, rz, h, dt, dtype="f32", max_sources=len(srcs),
+                      max_receivers=len(rec))
+    del vz_t, eps_t, delta_t
+    for ((pos, ap, aq), wav) in zip(srcs, wavs):
+        p.inject(torch.tensor(wav, dtype=torch.float32, device="cuda"), pos, ap, aq)
+    trp, trq = p.record(rec, T, record_q=True)
+    p.step(T)
+    fields = list(p.state())
+    torch.cuda.synchronize()
+    cfg = p.kernel_config
+    p.close()
+    del p
+    traces = {"traces_p": trp.double().cpu().numpy(), "traces_q": trq.double().cpu().numpy()}
+    names = ("p", "p_prev", "q", "q_prev")
+    for ((pos, ap, aq), wav), b in zip(zip(srcs, wavs), boxes):
+        (z0, z1), (y0, y1), (x0, x1) = b
+        shape = (z1 - z0, y1 - y0, x1 - x0)
+        sub = lambda prof: np.broadcast_to(prof[z0:z1, None, None], shape).copy()
+        inside = [j for j in range(len(rec)) if in_box(rec[j], b)]
+        ref = oracle_mod.vti_forward(sub(vz_z), sub(eps_z), sub(delta_z), h, dt, rxy, rz, T,
+                                     zc=zc[z0: z1 + 2 * rz],
+                                     sources=[((pos[0] - x0, pos[1] - y0, pos[2] - z0), wav, ap, aq)],
+                                     receivers=rec[inside] - np.array([x0, y0, z0]))
+        errs = {f: rel_l2(fields[i][z0:z1, y0:y1, x0:x1].double().cpu().numpy(), ref[f]) for i, f in enumerate(names)}
+        errs.update({f: rel_l2(traces[f][:, inside], ref[f]) for f in ("traces_p", "traces_q")})
+        say(f"box around {pos}: " + ", ".join(f"{k} {v:.2e}" for k, v in errs.items()) + f" [{cfg}]")
+        assert np.linalg.norm(ref["p"]) > 0 and all(e <= 1e-4 for e in errs.values()), errs
+        for fld in fields:
+            fld[z0:z1, y0:y1, x0:x1] = 0
+    outside = [j for j in range(len(rec)) if not any(in_box(rec[j], b) for b in boxes)]
+    assert len(outside) == 2 and not traces["traces_p"][:, outside].any() and not traces["traces_q"][:, outside].any()
+    assert all(int(torch.count_nonzero(fld)) == 0 for fld in fields)
+    del fields, trp, trq
+    torch.cuda.empty_cache()
+
+
 _VTI_PAIRS = [(2, 1), (2, 2), (4, 1), (4, 2), (4, 4), (8, 1), (8, 2), (8, 4), (8, 8), (12, 1), (12, 2), (12, 4), (12, 8)]
 
 
