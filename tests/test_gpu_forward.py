@@ -151,6 +151,11 @@ def test_full_grid_384_r8(oracle_mod):
     _full_grid_case(oracle_mod, workloads.c3_3d_noise(), 16, 22)
 
 
+def test_full_grid_384_r8_fp64(oracle_mod):
+    # FP64 parity mode with the largest radius at a full-size grid (its 32x16 tile)
+    _full_grid_case(oracle_mod, workloads.c3_3d_noise(), 8, 25, dtype="f64")
+
+
 def _energy(u1, u0, c, w):
     """E^{n+1/2} = (u^{n+1} - u^n)^T C^-1 (u^{n+1} - u^n) - (u^{n+1})^T Lh u^n with Lh the
     dimensionless stencil (zero outside the grid), C = (v dt / h)^2: constant in n for the
