@@ -51,7 +51,8 @@ def _gpu_gradient(v, pb, obs):
 
 @pytest.mark.parametrize("dtype,tol", [("f64", 1e-9), ("f32", 1e-3)])
 @pytest.mark.parametrize("shape,r,T,K", [((20, 24, 28), 4, 120, 25), ((18, 21, 19), 8, 90, 40),
-                                         ((60, 70), 2, 200, 30)])
+                                         ((60, 70), 2, 200, 30),
+                                         ((80, 112, 160), 4, 150, 30)])  # 160 wide: the ragged-row adjoint tile
 def test_adjoint_gradient_vs_oracle(oracle_mod, shape, r, T, K, dtype, tol):
     v, pb, obs = _problem(oracle_mod, shape, r, T, K, dtype, seed=r)
     say(f"adjoint {dtype} shape={shape} r={r} T={T} K={K}")
