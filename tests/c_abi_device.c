@@ -2,14 +2,19 @@
  * GPU, with no Python and no torch: device memory comes from the HIP runtime's C API.
  *
  *   c_abi_device DTYPE(f32|f64) NX NY NZ R H DT NSTEPS SX SY SZ F0 T0 VEL.bin REC.bin NREC
- *                OUT_U.bin OUT_TRACES.bin
+ *                OUT_U.bin OUT_TRACES.bin [RESID.bin OUT_GRAD.bin]
  *
  * VEL.bin: dense velocity [NZ][NY][NX] in DTYPE; REC.bin: int32 [NREC][3] receiver
  * positions.  The program creates a context, computes Ricker samples on the device
  * (fd_ricker), registers the source and receivers, steps NSTEPS times, and writes the
  * dense u^NSTEPS and the traces [NSTEPS][NREC] (DTYPE) to the output files.  It prints
- * "step N" and "config NAME" and exits non-zero on any error.  Compiled and run by
- * test_gpu_c_abi.py. */
+ * "step N" and "config NAME" and exits non-zero on any error.  With RESID.bin (the
+ * residual [NSTEPS][NREC] in DTYPE) it instead runs the gradient with every forward
+ * state kept: NSTEPS + 1 padded fields (fd_field_bytes each; ghosts cleared by
+ * fd_clear_ghosts, the two starting fields zeroed), the forward pass by fd_step_record
+ * into them (traces recorded), the adjoint by fd_adjoint_stored over the whole run, and
+ * dJ/dv by fd_gradient_finish, written dense to OUT_GRAD.bin; OUT_U.bin then holds
+ * u^{NSTEPS-1}.  Compiled and run by test_gpu_c_abi.py. */
 #include <stdint.h>
 #include <stdio.h>
 #include <stdlib.h>
@@ -58,9 +63,65 @@ static int write_file(const char *path, const void *p, size_t bytes)
     return n != bytes;
 }
 
+/* The gradient mode (see the header comment): every forward state kept, no recompute. */
+static int gradient(fd_ctx *ctx, const fd_grid *g, int r, fd_dtype dt_code, size_t es, size_t npts, int64_t T,
+                    int64_t nrec, const void *d_v, void *d_u, const char *resid_path, const char *grad_path,
+                    hipStream_t stream)
+{
+    size_t fb = 0;
+    FD_OK_(fd_field_bytes(g, r, dt_code, &fb));
+    char *states, *mu, *grad;
+    void *d_resid, *d_gout;
+    HIP_OK(hipMalloc((void **)&states, (size_t)(T + 1) * fb));
+    HIP_OK(hipMalloc((void **)&mu, 2 * fb));
+    HIP_OK(hipMalloc((void **)&grad, fb));
+    HIP_OK(hipMalloc(&d_resid, (size_t)T * (size_t)nrec * es));
+    HIP_OK(hipMalloc(&d_gout, npts * es));
+    void *h_resid = read_file(resid_path, (size_t)T * (size_t)nrec * es);
+    if (!h_resid) {
+        fprintf(stderr, "cannot read the residual\n");
+        return 3;
+    }
+    HIP_OK(hipMemcpy(d_resid, h_resid, (size_t)T * (size_t)nrec * es, hipMemcpyHostToDevice));
+    HIP_OK(hipMemsetAsync(mu, 0, 2 * fb, stream));
+    HIP_OK(hipMemsetAsync(grad, 0, fb, stream));
+    /* field k holds u^k (k < T); field T holds u^{-1} = 0 and then takes u^T */
+    HIP_OK(hipMemsetAsync(states, 0, fb, stream));
+    HIP_OK(hipMemsetAsync(states + (size_t)T * fb, 0, fb, stream));
+    FD_OK_(fd_clear_ghosts(ctx, states, T + 1));
+    const char *prev = states + (size_t)T * fb, *cur = states;
+    for (int64_t k = 0; k < T; ++k) {
+        char *out = k + 1 < T ? states + (size_t)(k + 1) * fb : states + (size_t)T * fb;
+        FD_OK_(fd_step_record(ctx, cur, prev, out, k));
+        prev = cur;
+        cur = out;
+    }
+    FD_OK_(fd_adjoint_stored(ctx, states, 0, T, mu, d_resid, 1.0, grad, NULL));
+    FD_OK_(fd_gradient_finish(ctx, grad, d_v, d_gout, 1.0));
+    int64_t step = -1;
+    FD_OK_(fd_set_state(ctx, states + (size_t)(T - 1) * fb, NULL, T - 1, FD_PADDED));
+    FD_OK_(fd_get_state(ctx, d_u, NULL, &step, FD_DENSE));
+    FD_OK_(fd_sync(ctx));
+    void *h_g = malloc(npts * es);
+    if (!h_g) return 4;
+    HIP_OK(hipMemcpy(h_g, d_gout, npts * es, hipMemcpyDeviceToHost));
+    if (write_file(grad_path, h_g, npts * es)) {
+        fprintf(stderr, "cannot write the gradient\n");
+        return 5;
+    }
+    free(h_g);
+    free(h_resid);
+    HIP_OK(hipFree(states));
+    HIP_OK(hipFree(mu));
+    HIP_OK(hipFree(grad));
+    HIP_OK(hipFree(d_resid));
+    HIP_OK(hipFree(d_gout));
+    return 0;
+}
+
 int main(int argc, char **argv)
 {
-    if (argc != 19) {
+    if (argc != 19 && argc != 21) {
         fprintf(stderr, "usage: see the header comment of c_abi_device.c\n");
         return 2;
     }
@@ -104,10 +165,16 @@ int main(int argc, char **argv)
     FD_OK_(fd_ricker(d_wav, T, dt, f0, t0, dt_code, stream));
     FD_OK_(fd_inject(ctx, d_wav, T, src, 1.0));
     FD_OK_(fd_record(ctx, h_rec, nrec, d_tr, T));
-    FD_OK_(fd_step(ctx, T));
     int64_t step = -1;
-    FD_OK_(fd_get_state(ctx, d_u, NULL, &step, FD_DENSE));
-    FD_OK_(fd_sync(ctx));
+    if (argc == 19) {
+        FD_OK_(fd_step(ctx, T));
+        FD_OK_(fd_get_state(ctx, d_u, NULL, &step, FD_DENSE));
+        FD_OK_(fd_sync(ctx));
+    } else {
+        int st = gradient(ctx, &g, r, dt_code, es, npts, T, nrec, d_v, d_u, argv[19], argv[20], stream);
+        if (st) return st;
+        step = T;
+    }
     printf("step %lld\nconfig %s\n", (long long)step, fd_kernel_config(ctx));
 
     void *h_u = malloc(npts * es), *h_tr = malloc((size_t)T * (size_t)nrec * es);
