@@ -110,6 +110,27 @@ def test_kept_states_bitwise_checkpointed(oracle_mod, shape, r, T):
     assert torch.equal(tr_all, tr_ck)
 
 
+@pytest.mark.parametrize("i", range(6))
+def test_kept_states_random_cases_bitwise(oracle_mod, i):
+    # random shapes (2-D and 3-D, ragged against every tile), radii, dtypes, segment
+    # lengths and blocking: the two ways of keeping the forward states give the same bits
+    rng = np.random.default_rng(900 + i)
+    ndim = 3 if i % 3 else 2
+    r = int(rng.integers(1, 9))
+    shape = tuple(int(x) for x in rng.integers(9, 41, size=ndim))
+    T = int(rng.integers(20, 80))
+    dtype = "f64" if i % 2 else "f32"
+    v, pb, obs = _problem(oracle_mod, shape, r, T, int(rng.integers(1, T + 1)), dtype, seed=900 + i)
+    pb.blocked = bool(rng.integers(0, 2))
+    got = {}
+    for mode in ("all", "checkpoint"):
+        pb.states = mode
+        say(f"random case {i}: {shape} r={r} T={T} {dtype} K={pb.ckpt} blocked={pb.blocked} states {mode}")
+        got[mode] = _gpu_gradient(v, pb, obs)[1]
+    assert np.linalg.norm(got["all"]) > 0
+    assert np.array_equal(got["all"], got["checkpoint"])
+
+
 @pytest.mark.parametrize("r,ncfg", [(4, 6), (8, 2)])
 def test_adjoint_tile_shapes_bitwise(oracle_mod, r, ncfg):
     # every registered adjoint tile runs the same per-point arithmetic, so the gradient
