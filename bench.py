@@ -503,7 +503,7 @@ def run_gradient():
     import workloads
     from paper_1410_1387_amd import Propagator
     from paper_1410_1387_amd import fdwave as F
-    from paper_1410_1387_amd.autograd import GradientProblem, WaveProp, misfit
+    from paper_1410_1387_amd.autograd import GradientProblem, WaveProp, keeps_all_states, misfit
 
     case = workloads.GradientCase()
     v_true, v0 = case.models()
@@ -534,11 +534,11 @@ def run_gradient():
         t2 = time.perf_counter()
         return t1 - t0, t2 - t1, float(J.detach()), v.grad
 
-    from paper_1410_1387_amd.autograd import keeps_all_states
-
+    # keep every forward state when they fit (decided once, then fixed for both runs)
     fb = F.fd_field_bytes((case.n,) * 3, case.r, "f32")
-    once()
     kept = keeps_all_states(pb, fb, v0t.device)
+    pb.states = "all" if kept else "checkpoint"
+    once()
     tf, tb, J, g = once()
     n3 = case.n ** 3
     finite = bool(torch.isfinite(g).all().item())
